@@ -1,0 +1,212 @@
+/*
+ * gtls.h -- C ABI of the MI355X (gfx950) Transit Least Squares search.
+ *
+ * The library implements the search the GTLS paper (Hu, Ge, Jin, Willis,
+ * "GTLS: A GPU-accelerated method for periodic transit detection") builds
+ * its GPU pipeline around: for every trial period, fold the light curve and
+ * sort it by phase (Sect. 2.3.1), pad it cyclically (Sect. 2.3.2), slide a
+ * limb-darkened transit template of every trial duration over it, fit a depth
+ * and a chi-square per window (Sect. 2.3.3-2.3.4), keep the minimum over
+ * duration and T0, and turn chi2(P) into the SDE periodogram (Sect. 2.4).
+ *
+ * Conventions shared by every call:
+ *   - All sizes are explicit.  Arrays are contiguous, C order, FP64 unless
+ *     stated.  Days are the time unit of times, periods and durations.
+ *   - Ownership: the caller owns every input and output buffer; the library
+ *     never frees them and keeps no pointer after a call returns.  A context
+ *     owns its device scratch (grown on demand, freed by gtls_destroy).
+ *   - Host-pointer calls are synchronous.  *_dev calls take device pointers,
+ *     enqueue work on the context's stream and return; results are valid
+ *     after gtls_sync (or any later synchronisation of that stream).
+ *   - Errors: a negative gtls_status; gtls_last_error(ctx) then holds a
+ *     message.  On error the contents of outputs are unspecified, except that
+ *     tls_search sets out->best_period to -1.
+ *   - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef GTLS_H
+#define GTLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GTLS_OK = 0,
+    GTLS_EINVAL = -1,    /* an argument failed validation                 */
+    GTLS_ENOMEM = -2,    /* device or host allocation failed              */
+    GTLS_EDEVICE = -3,   /* no usable gfx950 device, or a HIP call failed */
+    GTLS_EINTERNAL = -4  /* a kernel left a result unfilled               */
+} gtls_status;
+
+/* Arithmetic of the flux path.  Time and phase are FP64 in both. */
+enum { GTLS_FP64 = 0, GTLS_FP32C = 1 };
+
+/* Depth rule per window.
+ * WLS: weighted least-squares depth c/b (clamped at 0).
+ * MEAN: the moving-average depth of Sect. 2.3.3, taken as the window's mean
+ *       deficit over the template's mean (clamped at 0), from prefix sums. */
+enum { GTLS_DEPTH_WLS = 0, GTLS_DEPTH_MEAN = 1 };
+
+typedef struct gtls_ctx gtls_ctx;
+
+typedef struct {
+    double dt0;            /* T0 step as a fraction of the transit's points
+                              (Sect. 2.5, N_skip = n_IT * dt0, floored, >= 1);
+                              0 evaluates every offset                        */
+    int32_t envelope;      /* 1: k_min P^(-2/3) <= T14/P <= k_max P^(-2/3),
+                              P in seconds (Sect. 2.2.2); 0: only q_cap      */
+    double k_min, k_max;   /* s^(2/3); defaults 20.05 and 620.84              */
+    double q_cap;          /* T14/P upper cap, default 0.15, always applied   */
+    int32_t depth_mode;    /* GTLS_DEPTH_WLS (default) or GTLS_DEPTH_MEAN      */
+    int32_t precision;     /* GTLS_FP64 (default) or GTLS_FP32C                */
+    int32_t median_window; /* odd running-median width of the SDE detrend, 91 */
+} gtls_params;
+
+/* Per-period outputs (arrays of n_periods, caller-owned) and summaries.
+ *   chi2[n]       minimum chi-square over durations and T0 at period n
+ *   best_dur[n]   index into duration_grid of that minimum, -1 if no duration
+ *                 passes the envelope at this period
+ *   best_start[n] window start as an index into the phase-sorted order of
+ *                 this period (the padded curve, Sect. 2.3.2), -1 if none
+ *   depth[n]      fitted depth of that window (fraction of unit flux)
+ *   t0[n]         mid-transit: the phase of the window's middle point,
+ *                 moved to the first epoch at or after min(time); NaN if none
+ *   sr, sde_raw, sde [n]  signal residue chi2_min/chi2, its standardised
+ *                 form, and that minus its running median (Sect. 2.4)
+ *   chi2_null     sum of w (y - 1)^2, the flat-model chi-square
+ *   best_period   first index of the largest SDE
+ *   sde_max       SDE at best_period
+ *   n_evals       number of (period, duration, T0) windows evaluated
+ *   n_macs        template multiply-adds of those windows (sum of D)
+ * Any array pointer may be NULL to skip that output (host calls only). */
+typedef struct {
+    double *chi2;
+    int32_t *best_dur;
+    int32_t *best_start;
+    double *depth;
+    double *t0;
+    double *sr;
+    double *sde_raw;
+    double *sde;
+    double chi2_null;
+    int32_t best_period;
+    double sde_max;
+    int64_t n_evals;
+    int64_t n_macs;
+} gtls_result;
+
+/* Scalar summary written to device memory by tls_search_dev. */
+typedef struct {
+    double chi2_null;
+    double sde_max;
+    int64_t n_evals;
+    int64_t n_macs;
+    int32_t best_period;
+    int32_t pad_;
+} gtls_summary;
+
+/* Per-stage kernel timing, accumulated while profiling is on.  Stages:
+ * 0 per-point preparation and chi2_0, 1 fold + sort + padding, 2 template
+ * slide, 3 per-period reduction, 4 periodogram statistics. */
+#define GTLS_N_STAGES 5
+typedef struct {
+    double ms[8];          /* summed kernel time per stage (HIP events on the
+                              context's stream, bracketing each launch)    */
+    int64_t launches[8];   /* kernel launches per stage                    */
+} gtls_profile;
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
+ * run on, or NULL for a stream the context creates.  Returns GTLS_EDEVICE
+ * when no gfx950 device is visible.  *ctx is NULL on failure. */
+gtls_status gtls_create(gtls_ctx **ctx, int device, void *hip_stream);
+
+/* Release a context and its device scratch.  NULL is a no-op. */
+void gtls_destroy(gtls_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of the last failed
+ * gtls_create when ctx is NULL).  Valid until the next call on ctx. */
+const char *gtls_last_error(const gtls_ctx *ctx);
+
+/* Turn per-stage timing on (1) or off (0); turning it on clears the
+ * counters.  Timing adds two event records per launch on the stream. */
+gtls_status gtls_profile_enable(gtls_ctx *ctx, int on);
+
+/* Wait for the stream and return the accumulated per-stage timing. */
+gtls_status gtls_profile_read(gtls_ctx *ctx, gtls_profile *out);
+
+/* Fill p with the defaults listed in gtls_params. */
+void gtls_params_default(gtls_params *p);
+
+/* Wait for all work enqueued on the context's stream. */
+gtls_status gtls_sync(gtls_ctx *ctx);
+
+/* The whole search on host arrays (Sect. 2.3-2.4).
+ *   time, flux, dy [n]: one light curve; time need not be sorted, dy > 0,
+ *     everything finite, |1 - flux| < 1024, 3 <= n < 2^31.
+ *   period_grid [n_periods]: strictly increasing, > 0 (days).
+ *   duration_grid [n_durations]: > 0, non-decreasing (days).
+ *   tmpl [n_tmpl]: unit-depth transit samples at x_m = (m + 1/2)/n_tmpl,
+ *     values in (0, 1], maximum exactly 1, n_tmpl >= 2.
+ *   params: NULL for defaults.
+ * Writes the outputs of gtls_result.  Synchronous. */
+gtls_status tls_search(gtls_ctx *ctx, const double *time, const double *flux,
+                       const double *dy, int64_t n, const double *period_grid,
+                       int32_t n_periods, const double *duration_grid,
+                       int32_t n_durations, const double *tmpl, int32_t n_tmpl,
+                       const gtls_params *params, gtls_result *out);
+
+/* Same search on device arrays, enqueued on the context's stream.
+ * Inputs are device pointers of the sizes above; the seven per-period
+ * outputs (chi2, best_dur, best_start, depth, t0, sde_raw, sde) are device
+ * arrays of n_periods and must all be non-NULL (sr may be NULL); summary is a
+ * device pointer.  Validation reads only sizes and params (device data is not
+ * inspected); invalid device data gives unspecified results. */
+gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux,
+                           const double *dy, int64_t n, const double *period_grid,
+                           int32_t n_periods, const double *duration_grid,
+                           int32_t n_durations, const double *tmpl, int32_t n_tmpl,
+                           const gtls_params *params, double *chi2, int32_t *best_dur,
+                           int32_t *best_start, double *depth, double *t0, double *sr,
+                           double *sde_raw, double *sde, gtls_summary *summary);
+
+/* Fold and phase-sort only (Sect. 2.3.1): perm[k * n + i] is the input index
+ * of the i-th point in phase order at periods[k]; ties in phase keep input
+ * order.  Host arrays; perm has n_periods * n entries. */
+gtls_status tls_fold_sort(gtls_ctx *ctx, const double *time, int64_t n,
+                          const double *periods, int32_t n_periods, int32_t *perm);
+
+/* Periodogram statistics alone (Sect. 2.4) on a host chi2 array of n > 0
+ * values: sr, sde_raw, sde [n] (any may be NULL) and the first argmax of sde.
+ * window must be odd and >= 1. */
+gtls_status tls_sde(gtls_ctx *ctx, const double *chi2, int32_t n, int32_t window,
+                    double *sr, double *sde_raw, double *sde, int32_t *best);
+
+/* ---------------- host-side helpers (no device needed) ---------------- */
+
+/* Cubic frequency grid of Sect. 2.2.1 as ascending periods in days.
+ * baseline_days S > 0, os > 0, stellar mass/radius in solar units.
+ * pmin_days = 0 uses the Roche limit f_max; pmax_days = 0 uses S/2.
+ * Writes at most cap periods; *n_out is the full count (call with cap = 0
+ * to size).  GTLS_EINVAL if cap is non-zero and too small. */
+gtls_status gtls_period_grid_ofir(double baseline_days, double os, double m_sun,
+                                  double r_sun, double pmin_days, double pmax_days,
+                                  double *out, int32_t cap, int32_t *n_out);
+
+/* n log-spaced durations (days) between the envelope extremes over
+ * [pmin_days, pmax_days] (Sect. 2.2.2). */
+gtls_status gtls_duration_grid(double pmin_days, double pmax_days, int32_t n,
+                               double k_min, double k_max, double q_cap, double *out);
+
+/* m samples of a unit-depth quadratic-limb-darkened transit (u1, u2), planet
+ * radius p (stellar radii), impact parameter b, at x = (k + 1/2)/m of the
+ * T1-T4 chord; the largest sample is exactly 1. */
+gtls_status gtls_template_quadratic(double u1, double u2, double p, double b,
+                                    int32_t m, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GTLS_H */

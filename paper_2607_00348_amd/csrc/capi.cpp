@@ -1,0 +1,335 @@
+// C ABI of the search: argument validation, contexts, and the host-pointer
+// wrappers around the device pipeline in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "gtls_impl.hpp"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+gtls_status fail(gtls_ctx* ctx, gtls_status code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+gtls_status hip_fail(gtls_ctx* ctx, hipError_t e, const char* where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? GTLS_ENOMEM : GTLS_EDEVICE, m);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+gtls_status check_params(gtls_ctx* ctx, const gtls_params& p) {
+    if (!(p.dt0 >= 0.0) || !std::isfinite(p.dt0)) return fail(ctx, GTLS_EINVAL, "dt0 must be finite and >= 0");
+    if (!(p.q_cap > 0.0) || !(p.q_cap <= 1.0)) return fail(ctx, GTLS_EINVAL, "q_cap must be in (0, 1]");
+    if (p.envelope != 0 && p.envelope != 1) return fail(ctx, GTLS_EINVAL, "envelope must be 0 or 1");
+    if (p.envelope && (!(p.k_min > 0.0) || !(p.k_max >= p.k_min) || !std::isfinite(p.k_max)))
+        return fail(ctx, GTLS_EINVAL, "envelope needs 0 < k_min <= k_max");
+    if (p.depth_mode != GTLS_DEPTH_WLS && p.depth_mode != GTLS_DEPTH_MEAN)
+        return fail(ctx, GTLS_EINVAL, "unknown depth_mode");
+    if (p.precision != GTLS_FP64) return fail(ctx, GTLS_EINVAL, "precision mode not available");
+    if (p.median_window < 1 || p.median_window > 1023 || (p.median_window % 2) == 0)
+        return fail(ctx, GTLS_EINVAL, "median_window must be odd and in [1, 1023]");
+    return GTLS_OK;
+}
+
+gtls_status check_sizes(gtls_ctx* ctx, int64_t n, int32_t np, int32_t nd, int32_t nt) {
+    if (n < 3 || n > 0x7fffffff) return fail(ctx, GTLS_EINVAL, "n must be in [3, 2^31)");
+    if (np < 1) return fail(ctx, GTLS_EINVAL, "n_periods must be >= 1");
+    if (nd < 1) return fail(ctx, GTLS_EINVAL, "n_durations must be >= 1");
+    if (nt < 2) return fail(ctx, GTLS_EINVAL, "n_tmpl must be >= 2");
+    return GTLS_OK;
+}
+
+gtls_status check_host_data(gtls_ctx* ctx, const double* t, const double* y, const double* dy, int64_t n,
+                            const double* per, int32_t np, const double* dur, int32_t nd, const double* tm,
+                            int32_t nt) {
+    if (!t || !y || !dy || !per || !dur || !tm) return fail(ctx, GTLS_EINVAL, "null input array");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(t[i]) || !std::isfinite(y[i])) return fail(ctx, GTLS_EINVAL, "non-finite time or flux");
+        if (!(std::fabs(1.0 - y[i]) < 1024.0)) return fail(ctx, GTLS_EINVAL, "flux must satisfy |1 - y| < 1024");
+        if (!(dy[i] > 0.0) || !std::isfinite(dy[i])) return fail(ctx, GTLS_EINVAL, "dy must be finite and > 0");
+        if (!(1.0 / (dy[i] * dy[i]) < INFINITY)) return fail(ctx, GTLS_EINVAL, "dy too small");
+    }
+    for (int32_t k = 0; k < np; ++k) {
+        if (!(per[k] > 0.0) || !std::isfinite(per[k])) return fail(ctx, GTLS_EINVAL, "periods must be finite and > 0");
+        if (k > 0 && !(per[k] > per[k - 1])) return fail(ctx, GTLS_EINVAL, "periods must be strictly increasing");
+    }
+    for (int32_t k = 0; k < nd; ++k) {
+        if (!(dur[k] > 0.0) || !std::isfinite(dur[k])) return fail(ctx, GTLS_EINVAL, "durations must be finite and > 0");
+        if (k > 0 && !(dur[k] >= dur[k - 1])) return fail(ctx, GTLS_EINVAL, "durations must be non-decreasing");
+    }
+    double mx = 0.0;
+    for (int32_t k = 0; k < nt; ++k) {
+        if (!(tm[k] > 0.0) || !(tm[k] <= 1.0)) return fail(ctx, GTLS_EINVAL, "template values must be in (0, 1]");
+        mx = std::fmax(mx, tm[k]);
+    }
+    if (mx != 1.0) return fail(ctx, GTLS_EINVAL, "template maximum must be exactly 1");
+    return GTLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gtls_params_default(gtls_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->dt0 = 0.0;
+    p->envelope = 1;
+    p->k_min = 20.05;
+    p->k_max = 620.84;
+    p->q_cap = 0.15;
+    p->depth_mode = GTLS_DEPTH_WLS;
+    p->precision = GTLS_FP64;
+    p->median_window = 91;
+}
+
+gtls_status gtls_create(gtls_ctx** out, int device, void* hip_stream) {
+    if (!out) return fail(nullptr, GTLS_EINVAL, "ctx pointer is null");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(nullptr, GTLS_EDEVICE, "no HIP device visible");
+    if (device < 0 || device >= count) return fail(nullptr, GTLS_EDEVICE, "device index out of range");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return fail(nullptr, GTLS_EDEVICE, hipGetErrorString(e));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, GTLS_EDEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, GTLS_EDEVICE, hipGetErrorString(e));
+    gtls_ctx* ctx = new gtls_ctx();
+    ctx->device = device;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete ctx;
+            return fail(nullptr, GTLS_EDEVICE, hipGetErrorString(e));
+        }
+        ctx->own_stream = true;
+    }
+    *out = ctx;
+    return GTLS_OK;
+}
+
+void gtls_destroy(gtls_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (gtls::DeviceBuffer* b : {&ctx->curve, &ctx->batch, &ctx->io, &ctx->sde_tmp})
+        if (b->ptr) (void)hipFree(b->ptr);
+    for (auto& p : ctx->pending) {
+        ctx->event_pool.push_back(p.start);
+        ctx->event_pool.push_back(p.stop);
+    }
+    for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* gtls_last_error(const gtls_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+gtls_status gtls_profile_enable(gtls_ctx* ctx, int on) {
+    if (!ctx) return GTLS_EINVAL;
+    hipError_t e = gtls::profile_collect(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile");
+    for (int k = 0; k < 8; ++k) {
+        ctx->prof_ms[k] = 0.0;
+        ctx->prof_launches[k] = 0;
+    }
+    ctx->profiling = on != 0;
+    return GTLS_OK;
+}
+
+gtls_status gtls_profile_read(gtls_ctx* ctx, gtls_profile* out) {
+    if (!ctx || !out) return GTLS_EINVAL;
+    hipError_t e = gtls::profile_collect(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "profile");
+    for (int k = 0; k < 8; ++k) {
+        out->ms[k] = ctx->prof_ms[k];
+        out->launches[k] = ctx->prof_launches[k];
+    }
+    return GTLS_OK;
+}
+
+gtls_status gtls_sync(gtls_ctx* ctx) {
+    if (!ctx) return GTLS_EINVAL;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? GTLS_OK : hip_fail(ctx, e, "stream synchronize");
+}
+
+gtls_status tls_search_dev(gtls_ctx* ctx, const double* time, const double* flux, const double* dy, int64_t n,
+                           const double* period_grid, int32_t n_periods, const double* duration_grid,
+                           int32_t n_durations, const double* tmpl, int32_t n_tmpl, const gtls_params* params,
+                           double* chi2, int32_t* best_dur, int32_t* best_start, double* depth, double* t0,
+                           double* sr, double* sde_raw, double* sde, gtls_summary* summary) {
+    if (!ctx) return GTLS_EINVAL;
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    gtls_status st = check_sizes(ctx, n, n_periods, n_durations, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if ((st = check_params(ctx, prm)) != GTLS_OK) return st;
+    if (!time || !flux || !dy || !period_grid || !duration_grid || !tmpl || !chi2 || !best_dur || !best_start ||
+        !depth || !t0 || !sde_raw || !sde || !summary)
+        return fail(ctx, GTLS_EINVAL, "null device pointer");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    // SR is needed internally; use scratch when the caller passes none.
+    double* srp = sr;
+    if (!srp) {
+        e = gtls::ensure(ctx, ctx->sde_tmp, align256(sizeof(double) * (size_t)n_periods));
+        if (e != hipSuccess) return hip_fail(ctx, e, "sde scratch");
+        srp = (double*)ctx->sde_tmp.ptr;
+    }
+    gtls::SearchArgs a{time, flux, dy, n, period_grid, n_periods, duration_grid, n_durations, tmpl, n_tmpl, prm,
+                       chi2, best_dur, best_start, depth, t0, srp, sde_raw, sde, summary};
+    e = gtls::run_search(ctx, a);
+    if (e != hipSuccess) return hip_fail(ctx, e, "search");
+    return GTLS_OK;
+}
+
+gtls_status tls_search(gtls_ctx* ctx, const double* time, const double* flux, const double* dy, int64_t n,
+                       const double* period_grid, int32_t n_periods, const double* duration_grid,
+                       int32_t n_durations, const double* tmpl, int32_t n_tmpl, const gtls_params* params,
+                       gtls_result* out) {
+    if (!ctx) return GTLS_EINVAL;
+    if (out) out->best_period = -1;
+    if (!out) return fail(ctx, GTLS_EINVAL, "out is null");
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    gtls_status st = check_sizes(ctx, n, n_periods, n_durations, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if ((st = check_params(ctx, prm)) != GTLS_OK) return st;
+    st = check_host_data(ctx, time, flux, dy, n, period_grid, n_periods, duration_grid, n_durations, tmpl, n_tmpl);
+    if (st != GTLS_OK) return st;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+
+    const size_t np = (size_t)n_periods, nn = (size_t)n;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t o_t = take(8 * nn), o_y = take(8 * nn), o_dy = take(8 * nn), o_p = take(8 * np),
+                 o_d = take(8 * (size_t)n_durations), o_tm = take(8 * (size_t)n_tmpl), o_chi2 = take(8 * np),
+                 o_bd = take(4 * np), o_bs = take(4 * np), o_dep = take(8 * np), o_t0 = take(8 * np),
+                 o_sr = take(8 * np), o_raw = take(8 * np), o_sde = take(8 * np), o_sum = take(sizeof(gtls_summary));
+    e = gtls::ensure(ctx, ctx->io, o);
+    if (e != hipSuccess) return hip_fail(ctx, e, "device buffers");
+    char* b = (char*)ctx->io.ptr;
+    hipStream_t s = ctx->stream;
+    struct Up { size_t off; const void* src; size_t bytes; } ups[] = {
+        {o_t, time, 8 * nn}, {o_y, flux, 8 * nn}, {o_dy, dy, 8 * nn}, {o_p, period_grid, 8 * np},
+        {o_d, duration_grid, 8 * (size_t)n_durations}, {o_tm, tmpl, 8 * (size_t)n_tmpl}};
+    for (const Up& u : ups) {
+        e = hipMemcpyAsync(b + u.off, u.src, u.bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "copy to device");
+    }
+    gtls::SearchArgs a{(double*)(b + o_t), (double*)(b + o_y), (double*)(b + o_dy), n, (double*)(b + o_p),
+                       n_periods, (double*)(b + o_d), n_durations, (double*)(b + o_tm), n_tmpl, prm,
+                       (double*)(b + o_chi2), (int32_t*)(b + o_bd), (int32_t*)(b + o_bs), (double*)(b + o_dep),
+                       (double*)(b + o_t0), (double*)(b + o_sr), (double*)(b + o_raw), (double*)(b + o_sde),
+                       (gtls_summary*)(b + o_sum)};
+    e = gtls::run_search(ctx, a);
+    if (e != hipSuccess) return hip_fail(ctx, e, "search");
+    struct Down { void* dst; size_t off; size_t bytes; } downs[] = {
+        {out->chi2, o_chi2, 8 * np}, {out->best_dur, o_bd, 4 * np}, {out->best_start, o_bs, 4 * np},
+        {out->depth, o_dep, 8 * np}, {out->t0, o_t0, 8 * np}, {out->sr, o_sr, 8 * np},
+        {out->sde_raw, o_raw, 8 * np}, {out->sde, o_sde, 8 * np}};
+    for (const Down& d : downs) {
+        if (!d.dst) continue;
+        e = hipMemcpyAsync(d.dst, b + d.off, d.bytes, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    }
+    gtls_summary sum;
+    e = hipMemcpyAsync(&sum, b + o_sum, sizeof(sum), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    out->chi2_null = sum.chi2_null;
+    out->best_period = sum.best_period;
+    out->sde_max = sum.sde_max;
+    out->n_evals = sum.n_evals;
+    out->n_macs = sum.n_macs;
+    if (sum.best_period < 0) return fail(ctx, GTLS_EINTERNAL, "no best period produced");
+    return GTLS_OK;
+}
+
+gtls_status tls_fold_sort(gtls_ctx* ctx, const double* time, int64_t n, const double* periods, int32_t n_periods,
+                          int32_t* perm) {
+    if (!ctx) return GTLS_EINVAL;
+    if (!time || !periods || !perm) return fail(ctx, GTLS_EINVAL, "null argument");
+    if (n < 1 || n > 0x7fffffff || n_periods < 1) return fail(ctx, GTLS_EINVAL, "bad sizes");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(time[i])) return fail(ctx, GTLS_EINVAL, "non-finite time");
+    for (int32_t k = 0; k < n_periods; ++k)
+        if (!(periods[k] > 0.0) || !std::isfinite(periods[k])) return fail(ctx, GTLS_EINVAL, "bad period");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    const size_t o_t = 0, o_p = align256(8 * (size_t)n), o_perm = align256(o_p + 8 * (size_t)n_periods),
+                 total = align256(o_perm + 4 * (size_t)n * n_periods);
+    e = gtls::ensure(ctx, ctx->io, total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "device buffers");
+    char* b = (char*)ctx->io.ptr;
+    hipStream_t s = ctx->stream;
+    e = hipMemcpyAsync(b + o_t, time, 8 * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_p, periods, 8 * (size_t)n_periods, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to device");
+    e = gtls::run_fold_sort(ctx, (double*)(b + o_t), n, (double*)(b + o_p), n_periods, (int32_t*)(b + o_perm));
+    if (e != hipSuccess) return hip_fail(ctx, e, "fold sort");
+    e = hipMemcpyAsync(perm, b + o_perm, 4 * (size_t)n * n_periods, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    return GTLS_OK;
+}
+
+gtls_status tls_sde(gtls_ctx* ctx, const double* chi2, int32_t n, int32_t window, double* sr, double* sde_raw,
+                    double* sde, int32_t* best) {
+    if (!ctx) return GTLS_EINVAL;
+    if (!chi2 || n < 1) return fail(ctx, GTLS_EINVAL, "chi2 must be a non-empty array");
+    if (window < 1 || window > 1023 || window % 2 == 0) return fail(ctx, GTLS_EINVAL, "window must be odd, 1..1023");
+    for (int32_t i = 0; i < n; ++i)
+        if (!(chi2[i] >= 0.0) || !std::isfinite(chi2[i])) return fail(ctx, GTLS_EINVAL, "chi2 must be finite, >= 0");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    const size_t nn = (size_t)n, o_c = 0, o_sr = align256(8 * nn), o_raw = align256(o_sr + 8 * nn),
+                 o_sde = align256(o_raw + 8 * nn), o_sum = align256(o_sde + 8 * nn),
+                 total = align256(o_sum + sizeof(gtls_summary));
+    e = gtls::ensure(ctx, ctx->io, total);
+    if (e != hipSuccess) return hip_fail(ctx, e, "device buffers");
+    char* b = (char*)ctx->io.ptr;
+    hipStream_t s = ctx->stream;
+    e = hipMemcpyAsync(b + o_c, chi2, 8 * nn, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to device");
+    e = gtls::run_sde(ctx, (double*)(b + o_c), n, window, (double*)(b + o_sr), (double*)(b + o_raw),
+                      (double*)(b + o_sde), (gtls_summary*)(b + o_sum));
+    if (e != hipSuccess) return hip_fail(ctx, e, "sde");
+    gtls_summary sum;
+    struct Down { void* dst; size_t off; } downs[] = {{sr, o_sr}, {sde_raw, o_raw}, {sde, o_sde}};
+    for (const Down& d : downs) {
+        if (!d.dst) continue;
+        e = hipMemcpyAsync(d.dst, b + d.off, 8 * nn, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    }
+    e = hipMemcpyAsync(&sum, b + o_sum, sizeof(sum), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    if (best) *best = sum.best_period;
+    return GTLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gtls.h"
+
+namespace gtls {
+
+// Per-(period, duration) best window, written by the slide kernel and read
+// by the per-period reduction.
+struct ItemBest {
+    double dchi2;   // best chi2 improvement; -inf when the duration is invalid
+    double depth;   // depth at that window
+    int32_t start;  // window start in phase order, -1 when invalid
+    int32_t d;      // points in the duration
+    int32_t evals;  // windows evaluated for this item
+    int32_t pad_;
+};
+
+struct SearchArgs {
+    // device inputs
+    const double* t;
+    const double* y;
+    const double* dy;
+    int64_t n;
+    const double* periods;
+    int32_t n_periods;
+    const double* durations;
+    int32_t n_durations;
+    const double* tmpl;
+    int32_t n_tmpl;
+    gtls_params prm;
+    // device outputs
+    double* chi2;
+    int32_t* best_dur;
+    int32_t* best_start;
+    double* depth;
+    double* t0;
+    double* sr;
+    double* sde_raw;
+    double* sde;
+    gtls_summary* summary;
+};
+
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace gtls
+
+struct gtls_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    // grow-only device scratch
+    gtls::DeviceBuffer curve;    // per-point arrays and scalars
+    gtls::DeviceBuffer batch;    // per-period-batch arrays
+    gtls::DeviceBuffer io;       // device copies for host-pointer calls
+    gtls::DeviceBuffer sde_tmp;  // SDE scratch
+    // per-stage timing (gtls_profile_enable / gtls_profile_read)
+    bool profiling = false;
+    double prof_ms[8] = {0};
+    int64_t prof_launches[8] = {0};
+    struct Pending {
+        int stage;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace gtls {
+
+// Launchers (kernels.hip).  Return hipSuccess or the first HIP error.
+hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a);
+hipError_t run_fold_sort(gtls_ctx* ctx, const double* t_dev, int64_t n, const double* periods_dev,
+                         int32_t n_periods, int32_t* perm_dev);
+hipError_t run_sde(gtls_ctx* ctx, const double* chi2_dev, int32_t n, int32_t window, double* sr_dev,
+                   double* raw_dev, double* sde_dev, gtls_summary* summary_dev);
+hipError_t ensure(gtls_ctx* ctx, DeviceBuffer& b, size_t bytes);
+hipError_t profile_collect(gtls_ctx* ctx);
+
+enum Stage { kStagePrep = 0, kStageSort = 1, kStageSlide = 2, kStageReduce = 3, kStageSde = 4 };
+
+// Brackets one kernel launch with events on the context's stream when
+// profiling is on.
+class StageTimer {
+  public:
+    StageTimer(gtls_ctx* ctx, int stage);
+    ~StageTimer();
+
+  private:
+    gtls_ctx* ctx_;
+    int stage_;
+    hipEvent_t stop_ = nullptr, start_ = nullptr;
+};
+
+}  // namespace gtls

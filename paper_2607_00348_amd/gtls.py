@@ -1,0 +1,263 @@
+"""ctypes binding of libgtls.so, the gfx950 TLS search.
+
+Argument marshalling only: every call goes straight to the C entry point of
+the same name declared in include/gtls.h.  Host arrays are numpy; the *_dev
+calls take device addresses (for example ``tensor.data_ptr()`` of a torch
+tensor on the GPU) and the stream is the one the context was created with.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgtls.so")
+
+GTLS_OK, GTLS_EINVAL, GTLS_ENOMEM, GTLS_EDEVICE, GTLS_EINTERNAL = 0, -1, -2, -3, -4
+GTLS_FP64, GTLS_FP32C = 0, 1
+GTLS_DEPTH_WLS, GTLS_DEPTH_MEAN = 0, 1
+
+EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_default", "gtls_sync",
+            "gtls_profile_enable", "gtls_profile_read",
+            "tls_search", "tls_search_dev", "tls_fold_sort", "tls_sde", "gtls_period_grid_ofir",
+            "gtls_duration_grid", "gtls_template_quadratic"]
+
+
+class gtls_params(ctypes.Structure):
+    _fields_ = [("dt0", ctypes.c_double), ("envelope", ctypes.c_int32), ("k_min", ctypes.c_double),
+                ("k_max", ctypes.c_double), ("q_cap", ctypes.c_double), ("depth_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("median_window", ctypes.c_int32)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class gtls_result(ctypes.Structure):
+    _fields_ = [("chi2", _dp), ("best_dur", _ip), ("best_start", _ip), ("depth", _dp), ("t0", _dp),
+                ("sr", _dp), ("sde_raw", _dp), ("sde", _dp), ("chi2_null", ctypes.c_double),
+                ("best_period", ctypes.c_int32), ("sde_max", ctypes.c_double), ("n_evals", ctypes.c_int64),
+                ("n_macs", ctypes.c_int64)]
+
+
+class gtls_summary(ctypes.Structure):
+    _fields_ = [("chi2_null", ctypes.c_double), ("sde_max", ctypes.c_double), ("n_evals", ctypes.c_int64),
+                ("n_macs", ctypes.c_int64), ("best_period", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+STAGES = ("prep", "fold_sort", "slide", "reduce", "sde")
+
+
+class gtls_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+
+
+class GtlsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gtls error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.gtls_create.restype = ctypes.c_int
+        L.gtls_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+        L.gtls_destroy.restype = None
+        L.gtls_destroy.argtypes = [vp]
+        L.gtls_last_error.restype = ctypes.c_char_p
+        L.gtls_last_error.argtypes = [vp]
+        L.gtls_params_default.restype = None
+        L.gtls_params_default.argtypes = [ctypes.POINTER(gtls_params)]
+        L.gtls_sync.restype = ctypes.c_int
+        L.gtls_sync.argtypes = [vp]
+        L.gtls_profile_enable.restype = ctypes.c_int
+        L.gtls_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.gtls_profile_read.restype = ctypes.c_int
+        L.gtls_profile_read.argtypes = [vp, ctypes.POINTER(gtls_profile)]
+        L.tls_search.restype = ctypes.c_int
+        L.tls_search.argtypes = [vp, _dp, _dp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp, ctypes.c_int32,
+                                 _dp, ctypes.c_int32, ctypes.POINTER(gtls_params), ctypes.POINTER(gtls_result)]
+        L.tls_search_dev.restype = ctypes.c_int
+        L.tls_search_dev.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, ctypes.c_int32,
+                                     vp, ctypes.c_int32, ctypes.POINTER(gtls_params), vp, vp, vp, vp, vp, vp,
+                                     vp, vp, vp]
+        L.tls_fold_sort.restype = ctypes.c_int
+        L.tls_fold_sort.argtypes = [vp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _ip]
+        L.tls_sde.restype = ctypes.c_int
+        L.tls_sde.argtypes = [vp, _dp, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _ip]
+        L.gtls_period_grid_ofir.restype = ctypes.c_int
+        L.gtls_period_grid_ofir.argtypes = [ctypes.c_double] * 6 + [_dp, ctypes.c_int32, _ip]
+        L.gtls_duration_grid.restype = ctypes.c_int
+        L.gtls_duration_grid.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, _dp]
+        L.gtls_template_quadratic.restype = ctypes.c_int
+        L.gtls_template_quadratic.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int32, _dp]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _check(code: int, ctx=None):
+    if code != GTLS_OK:
+        raise GtlsError(code, lib().gtls_last_error(ctx).decode())
+
+
+def gtls_params_default(**overrides) -> gtls_params:
+    p = gtls_params()
+    lib().gtls_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """Owns a gtls_ctx on one HIP device; stream is a hipStream_t or None."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.ptr = ctypes.c_void_p()
+        _check(lib().gtls_create(ctypes.byref(self.ptr), int(device), ctypes.c_void_p(stream or 0)))
+
+    def close(self):
+        if self.ptr:
+            lib().gtls_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def gtls_create(device: int = 0, stream: int | None = None) -> Context:
+    return Context(device, stream)
+
+
+def gtls_sync(ctx: Context):
+    _check(lib().gtls_sync(ctx.ptr), ctx.ptr)
+
+
+def gtls_profile_enable(ctx: Context, on: bool = True):
+    _check(lib().gtls_profile_enable(ctx.ptr, int(bool(on))), ctx.ptr)
+
+
+def gtls_profile_read(ctx: Context) -> dict:
+    """{stage name: (summed ms, launches)} for the stages of gtls.h."""
+    p = gtls_profile()
+    _check(lib().gtls_profile_read(ctx.ptr, ctypes.byref(p)), ctx.ptr)
+    return {name: (p.ms[k], int(p.launches[k])) for k, name in enumerate(STAGES)}
+
+
+@dataclass
+class SearchResult:
+    chi2: np.ndarray
+    best_dur: np.ndarray
+    best_start: np.ndarray
+    depth: np.ndarray
+    t0: np.ndarray
+    sr: np.ndarray
+    sde_raw: np.ndarray
+    sde: np.ndarray
+    chi2_null: float
+    best_period: int
+    sde_max: float
+    n_evals: int
+    n_macs: int
+
+
+def tls_search(ctx: Context, time, flux, dy, period_grid, duration_grid, tmpl,
+               params: gtls_params | None = None) -> SearchResult:
+    t, y, e = _f64(time), _f64(flux), _f64(dy)
+    per, dur, tm = _f64(period_grid), _f64(duration_grid), _f64(tmpl)
+    npd = len(per)
+    out = {k: np.empty(npd) for k in ("chi2", "depth", "t0", "sr", "sde_raw", "sde")}
+    out["best_dur"] = np.empty(npd, dtype=np.int32)
+    out["best_start"] = np.empty(npd, dtype=np.int32)
+    res = gtls_result()
+    for k in ("chi2", "depth", "t0", "sr", "sde_raw", "sde"):
+        setattr(res, k, _p(out[k]))
+    res.best_dur = out["best_dur"].ctypes.data_as(_ip)
+    res.best_start = out["best_start"].ctypes.data_as(_ip)
+    prm = params if params is not None else gtls_params_default()
+    _check(lib().tls_search(ctx.ptr, _p(t), _p(y), _p(e), len(t), _p(per), npd, _p(dur), len(dur), _p(tm),
+                            len(tm), ctypes.byref(prm), ctypes.byref(res)), ctx.ptr)
+    return SearchResult(chi2_null=res.chi2_null, best_period=res.best_period, sde_max=res.sde_max,
+                        n_evals=res.n_evals, n_macs=res.n_macs, **out)
+
+
+def tls_search_dev(ctx: Context, time, flux, dy, n: int, period_grid, n_periods: int, duration_grid,
+                   n_durations: int, tmpl, n_tmpl: int, params: gtls_params | None, chi2, best_dur, best_start,
+                   depth, t0, sr, sde_raw, sde, summary):
+    """All array arguments are device addresses (ints); enqueues and returns."""
+    prm = params if params is not None else gtls_params_default()
+    v = ctypes.c_void_p
+    _check(lib().tls_search_dev(ctx.ptr, v(time), v(flux), v(dy), int(n), v(period_grid), int(n_periods),
+                                v(duration_grid), int(n_durations), v(tmpl), int(n_tmpl), ctypes.byref(prm),
+                                v(chi2), v(best_dur), v(best_start), v(depth), v(t0), v(sr), v(sde_raw), v(sde),
+                                v(summary)), ctx.ptr)
+
+
+def tls_fold_sort(ctx: Context, time, periods) -> np.ndarray:
+    t, per = _f64(time), _f64(np.atleast_1d(periods))
+    perm = np.empty((len(per), len(t)), dtype=np.int32)
+    _check(lib().tls_fold_sort(ctx.ptr, _p(t), len(t), _p(per), len(per), perm.ctypes.data_as(_ip)), ctx.ptr)
+    return perm
+
+
+def tls_sde(ctx: Context, chi2, window: int = 91):
+    c = _f64(chi2)
+    n = len(c)
+    sr, raw, sde = np.empty(n), np.empty(n), np.empty(n)
+    best = ctypes.c_int32(-1)
+    _check(lib().tls_sde(ctx.ptr, _p(c), n, int(window), _p(sr), _p(raw), _p(sde), ctypes.byref(best)), ctx.ptr)
+    return sr, raw, sde, int(best.value)
+
+
+def gtls_period_grid_ofir(baseline_days: float, os_factor: float = 3.0, m_sun: float = 1.0, r_sun: float = 1.0,
+                          pmin_days: float = 0.0, pmax_days: float = 0.0) -> np.ndarray:
+    n = ctypes.c_int32(0)
+    args = [float(baseline_days), float(os_factor), float(m_sun), float(r_sun), float(pmin_days), float(pmax_days)]
+    _check(lib().gtls_period_grid_ofir(*args, None, 0, ctypes.byref(n)))
+    out = np.empty(n.value)
+    _check(lib().gtls_period_grid_ofir(*args, _p(out), n.value, ctypes.byref(n)))
+    return out
+
+
+def gtls_duration_grid(pmin_days: float, pmax_days: float, n: int, k_min: float = 20.05, k_max: float = 620.84,
+                       q_cap: float = 0.15) -> np.ndarray:
+    out = np.empty(int(n))
+    _check(lib().gtls_duration_grid(float(pmin_days), float(pmax_days), int(n), float(k_min), float(k_max),
+                                    float(q_cap), _p(out)))
+    return out
+
+
+def gtls_template_quadratic(u1: float = 0.4, u2: float = 0.25, p: float = 0.01, b: float = 0.0,
+                            m: int = 1024) -> np.ndarray:
+    out = np.empty(int(m))
+    _check(lib().gtls_template_quadratic(float(u1), float(u2), float(p), float(b), int(m), _p(out)))
+    return out
