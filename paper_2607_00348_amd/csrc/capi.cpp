@@ -33,7 +33,7 @@ gtls_status check_params(gtls_ctx* ctx, const gtls_params& p) {
         return fail(ctx, GTLS_EINVAL, "envelope needs 0 < k_min <= k_max");
     if (p.depth_mode != GTLS_DEPTH_WLS && p.depth_mode != GTLS_DEPTH_MEAN)
         return fail(ctx, GTLS_EINVAL, "unknown depth_mode");
-    if (p.precision != GTLS_FP64) return fail(ctx, GTLS_EINVAL, "precision mode not available");
+    if (p.precision != GTLS_FP64 && p.precision != GTLS_FP32C) return fail(ctx, GTLS_EINVAL, "unknown precision");
     if (p.median_window < 1 || p.median_window > 1023 || (p.median_window % 2) == 0)
         return fail(ctx, GTLS_EINVAL, "median_window must be odd and in [1, 1023]");
     return GTLS_OK;
@@ -125,7 +125,7 @@ void gtls_destroy(gtls_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (gtls::DeviceBuffer* b : {&ctx->curve, &ctx->batch, &ctx->io, &ctx->sde_tmp})
+    for (gtls::DeviceBuffer* b : {&ctx->curve, &ctx->batch, &ctx->io, &ctx->sde_tmp, &ctx->table})
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto& p : ctx->pending) {
         ctx->event_pool.push_back(p.start);

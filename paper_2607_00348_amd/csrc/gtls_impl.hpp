@@ -13,13 +13,15 @@ namespace gtls {
 
 // Per-(period, duration) best window, written by the slide kernel and read
 // by the per-period reduction.
+// Items with every T0 offset are split into tiles of windows, one slot per
+// tile; strided items fill slot 0 only.  Slot 0 records how many are used.
 struct ItemBest {
-    double dchi2;   // best chi2 improvement; -inf when the duration is invalid
-    double depth;   // depth at that window
-    int32_t start;  // window start in phase order, -1 when invalid
-    int32_t d;      // points in the duration
-    int32_t evals;  // windows evaluated for this item
-    int32_t pad_;
+    double dchi2;    // best chi2 improvement; -inf when the duration is invalid
+    double depth;    // depth at that window
+    int32_t start;   // window start in phase order, -1 when invalid
+    int32_t d;       // points in the duration
+    int32_t evals;   // windows evaluated by this slot
+    int32_t ntiles;  // (slot 0) number of slots holding results
 };
 
 struct SearchArgs {
@@ -64,6 +66,7 @@ struct gtls_ctx {
     gtls::DeviceBuffer batch;    // per-period-batch arrays
     gtls::DeviceBuffer io;       // device copies for host-pointer calls
     gtls::DeviceBuffer sde_tmp;  // SDE scratch
+    gtls::DeviceBuffer table;    // template rows per point count D and per-D sums
     // per-stage timing (gtls_profile_enable / gtls_profile_read)
     bool profiling = false;
     double prof_ms[8] = {0};

@@ -229,12 +229,20 @@ struct SortArgs {
     gtls_params prm;
     uint64_t* keys_a;        // [bp][n] sorted (phase key << 32 | index)
     uint64_t* keys_b;        // [bp][n] ping-pong
-    double* rpad;            // [bp][pstride]
-    double* wpad;            // [bp][pstride] or null
-    __int128* pfx;           // [bp][pstride + 1] or null
+    void* rpad;              // [bp][pstride] double (FP64) or float (FP32C)
+    void* wpad;              // [bp][pstride] or null
+    void* pfx;               // [bp][pstride + 1] __int128 (FP64) or float2 (FP32C), or null
     int64_t pstride;
     int32_t* perm_out;       // optional [bp][n] copy of the permutation
+    int32_t f32;             // 1: FP32C storage of the padded curve and prefix sums
 };
+
+// Error-free sum of two floats (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
 
 __device__ __forceinline__ bool key_less(uint64_t a, uint64_t b, const double* __restrict__ t, double period) {
     double pa = phase_of(t[(uint32_t)a], period);
@@ -370,21 +378,31 @@ __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
     }
     __syncthreads();
     const int64_t npad = n + sh_dpad;
-    double* rp = a.rpad + (size_t)pl * a.pstride;
-    double* wp = a.wpad ? a.wpad + (size_t)pl * a.pstride : nullptr;
-    for (int64_t k = tid; k < npad; k += kSortThreads) {
-        const uint32_t idx = (uint32_t)A[k < n ? k : k - n];
-        rp[k] = a.r[idx];
-        if (wp) wp[k] = a.w[idx];
+    if (a.f32) {
+        float* rp = (float*)a.rpad + (size_t)pl * a.pstride;
+        float* wp = a.wpad ? (float*)a.wpad + (size_t)pl * a.pstride : nullptr;
+        for (int64_t k = tid; k < npad; k += kSortThreads) {
+            const uint32_t idx = (uint32_t)A[k < n ? k : k - n];
+            rp[k] = (float)a.r[idx];
+            if (wp) wp[k] = (float)a.w[idx];
+        }
+    } else {
+        double* rp = (double*)a.rpad + (size_t)pl * a.pstride;
+        double* wp = a.wpad ? (double*)a.wpad + (size_t)pl * a.pstride : nullptr;
+        for (int64_t k = tid; k < npad; k += kSortThreads) {
+            const uint32_t idx = (uint32_t)A[k < n ? k : k - n];
+            rp[k] = a.r[idx];
+            if (wp) wp[k] = a.w[idx];
+        }
     }
     if (a.perm_out) {
         int32_t* po = a.perm_out + (size_t)pl * n;
         for (int64_t k = tid; k < n; k += kSortThreads) po[k] = (int32_t)(uint32_t)A[k];
     }
-    if (a.pfx) {
+    if (a.pfx && !a.f32) {
         // Exact prefix sums of the integer deficits over the padded curve:
         // pfx[k] = sum_{m<k} u[perm[m mod n]].
-        __int128* pf = a.pfx + (size_t)pl * (a.pstride + 1);
+        __int128* pf = (__int128*)a.pfx + (size_t)pl * (a.pstride + 1);
         const int64_t chunk = (npad + kSortThreads - 1) / kSortThreads;
         const int64_t c0 = (int64_t)tid * chunk, c1 = min(npad, c0 + chunk);
         __int128 s = 0;
@@ -406,19 +424,104 @@ __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
             run += (__int128)a.u[(uint32_t)A[k < n ? k : k - n]];
             pf[k + 1] = run;
         }
+    } else if (a.pfx) {
+        // FP32C: Kahan-compensated prefix sums of (float)(1 - y): each
+        // position stores an unevaluated (hi, lo) pair; chunk totals are
+        // combined by one thread with the same compensation.
+        float2* pf = (float2*)a.pfx + (size_t)pl * (a.pstride + 1);
+        float2* part = (float2*)sh_part;
+        const int64_t chunk = (npad + kSortThreads - 1) / kSortThreads;
+        const int64_t c0 = (int64_t)tid * chunk, c1 = min(npad, c0 + chunk);
+        float hi = 0.f, lo = 0.f;
+        for (int64_t k = c0; k < c1; ++k) {
+            const float x = (float)ldexp((double)a.u[(uint32_t)A[k < n ? k : k - n]], -53);
+            float sum, err;
+            two_sum(hi, x, sum, err);
+            hi = sum;
+            lo += err;
+        }
+        part[tid] = make_float2(hi, lo);
+        __syncthreads();
+        if (tid == 0) {
+            float rh = 0.f, rl = 0.f;
+            for (int q = 0; q < kSortThreads; ++q) {
+                const float2 c = part[q];
+                part[q] = make_float2(rh, rl);
+                float sum, err;
+                two_sum(rh, c.x, sum, err);
+                rh = sum;
+                rl += err + c.y;
+            }
+        }
+        __syncthreads();
+        hi = part[tid].x;
+        lo = part[tid].y;
+        if (tid == 0) pf[0] = make_float2(0.f, 0.f);
+        for (int64_t k = c0; k < c1; ++k) {
+            const float x = (float)ldexp((double)a.u[(uint32_t)A[k < n ? k : k - n]], -53);
+            float sum, err;
+            two_sum(hi, x, sum, err);
+            hi = sum;
+            lo += err;
+            pf[k + 1] = make_float2(hi, lo);
+        }
     }
 }
 
 // ------------------------------------------------------------------------
-// Slide: one workgroup per (period, duration).
+// Template table: row D holds the D-point ideal transit, zero-padded to a
+// multiple of 32, so any (period, duration) item reads its template as a
+// uniform stream through the scalar cache.  FP32C keeps a float copy.  With
+// constant weights the per-window b = sum_k w s_k^2 and the template sum
+// s1 = sum_k s_k depend on D only; they are summed once per D, in FP64 and
+// in the same sequential order as a per-window evaluation.
+
+__host__ __device__ __forceinline__ int64_t trow_off(int64_t d) {
+    const int64_t m = d - 1, a = m / 32, b = m % 32;
+    return 32 * (16 * a * (a + 1) + (a + 1) * b);
+}
+__host__ __device__ __forceinline__ int64_t rup32(int64_t d) { return (d + 31) & ~(int64_t)31; }
+
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tmpl_table(const double* __restrict__ tm, int32_t nt, T* __restrict__ table) {
+    const int64_t d = (int64_t)blockIdx.x + 1;
+    T* row = table + trow_off(d);
+    const int64_t w = rup32(d);
+    for (int64_t k = threadIdx.x; k < w; k += 256) row[k] = (k < d) ? (T)resample(tm, nt, d, k) : (T)0;
+}
+
+__global__ __launch_bounds__(64) void k_tmpl_sums(const double* __restrict__ tm, int32_t nt, int64_t dmax,
+                                                  const uint64_t* misc, double* __restrict__ bsum,
+                                                  double* __restrict__ s1sum) {
+    const int64_t d = (int64_t)blockIdx.x * 64 + threadIdx.x + 1;
+    if (d > dmax) return;
+    const double wc = __longlong_as_double((long long)misc[kWminBits]);
+    double b = 0.0, s1 = 0.0;
+    for (int64_t k = 0; k < d; ++k) {
+        const double sv = resample(tm, nt, d, k);
+        b = fma(wc, sv * sv, b);
+        s1 = s1 + sv;
+    }
+    bsum[d] = b;
+    s1sum[d] = s1;
+}
+
+// ------------------------------------------------------------------------
+// Slide: one workgroup per (period, duration) item, or per window tile of
+// it.
 
 constexpr int kSlideThreads = 256;
-constexpr int kR = 16;                              // windows per lane
-constexpr int kTile = kSlideThreads * kR;           // windows per pass
-constexpr int kKC = 256;                            // template points per LDS chunk
-constexpr int kXs = kTile + kKC;                    // staged curve points
-__host__ __device__ constexpr int xpad(int e) { return e + 2 * (e >> 4); }
-constexpr int kXsPadded = xpad(kXs);
+constexpr int kR = 16;                              // consecutive windows per lane (unit stride)
+constexpr int kTile = kSlideThreads * kR;           // windows per tile
+constexpr int kKC = 256;                            // template points per staged chunk
+constexpr int kXs = kTile + kKC + kR;               // staged curve points
+// Padded LDS index: every 16 points get 16 bytes of padding, so the 64 lanes'
+// 16-point groups start on distinct bank quads.
+template <typename T>
+__host__ __device__ constexpr int xpad(int e) { return e + (int)(16 / sizeof(T)) * (e >> 4); }
 
 struct SlideArgs {
     const double* periods;   // batch-offset
@@ -426,15 +529,17 @@ struct SlideArgs {
     int32_t nd;
     int32_t bp;
     int64_t n;
-    const double* tmpl;
-    int32_t nt;
     gtls_params prm;
-    const double* rpad;
-    const double* wpad;
-    const __int128* pfx;
+    const void* rpad;        // T [bp][pstride]
+    const void* wpad;
+    const void* pfx;         // __int128 (FP64) or float2 (FP32C) [bp][pstride + 1]
     int64_t pstride;
     const uint64_t* misc;
-    ItemBest* items;         // [bp][nd]
+    const void* table;       // T template rows
+    const double* bsum;      // [D] constant-weight b
+    const double* s1sum;     // [D] template sums
+    ItemBest* items;         // [bp][nd][ntiles]
+    int32_t ntiles;          // window tiles per unit-stride item
 };
 
 struct Best {
@@ -464,167 +569,60 @@ __device__ __forceinline__ void fit(double c, double b, double usum, double s1, 
     }
 }
 
-template <bool MEAN>
-__device__ __forceinline__ double window_deficit(const __int128* __restrict__ pf, int64_t i, int64_t d) {
-    if (!MEAN) return 0.0;
-    return ldexp(i128_to_double(pf[i + d] - pf[i]), -53);
+// Sum of 1 - y over the window [i, i + d): exact from 128-bit prefix sums
+// (FP64), or from the compensated (hi, lo) float pairs (FP32C).
+template <typename T, bool MEAN>
+__device__ __forceinline__ double window_deficit(const void* pf_base, int64_t i, int64_t d) {
+    if constexpr (!MEAN) {
+        return 0.0;
+    } else if constexpr (sizeof(T) == 8) {
+        const __int128* pf = (const __int128*)pf_base;
+        return ldexp(i128_to_double(pf[i + d] - pf[i]), -53);
+    } else {
+        const float2* pf = (const float2*)pf_base;
+        const float2 e = pf[i + d], s = pf[i];
+        return ((double)e.x - (double)s.x) + ((double)e.y - (double)s.y);
+    }
 }
 
-template <bool VARW, bool MEAN>
-__global__ __launch_bounds__(kSlideThreads) void k_slide(SlideArgs a) {
-    __shared__ double s_sh[kKC];
-    __shared__ double s2_sh[kKC];
-    __shared__ double x_sh[kXsPadded];
-    __shared__ double xw_sh[VARW ? kXsPadded : 1];
-    __shared__ Best red[kSlideThreads / 64];
+struct ItemInfo {
+    bool valid;
+    int pl, j, tile;
+    double period;
+    int64_t d, stride;
+};
 
+// Work units in launch order: longest durations first, then window tile,
+// then period, so the costliest units start earliest.
+__device__ __forceinline__ ItemInfo item_info(const SlideArgs& a, int tiles) {
+    ItemInfo it;
+    const int per_j = tiles * a.bp;
+    const int jrev = blockIdx.x / per_j;
+    const int rem = blockIdx.x - jrev * per_j;
+    it.tile = rem / a.bp;
+    it.pl = rem - it.tile * a.bp;
+    it.j = a.nd - 1 - jrev;
+    it.period = a.periods[it.pl];
+    const double dur = a.durations[it.j];
+    it.valid = duration_valid(it.period, dur, a.prm);
+    it.d = it.valid ? points_in(a.n, it.period, dur) : 0;
+    it.stride = it.valid ? t0_stride(it.d, a.prm.dt0) : 1;
+    return it;
+}
+
+__device__ __forceinline__ ItemBest* item_slot(const SlideArgs& a, const ItemInfo& it) {
+    return a.items + ((size_t)it.pl * a.nd + it.j) * a.ntiles + it.tile;
+}
+
+// Block-wide first-best (largest dchi2, then smallest start) -> item slot.
+__device__ __forceinline__ void store_best(Best best, const SlideArgs& a, const ItemInfo& it, Best* red,
+                                           int64_t evals, int ntiles) {
     const int tid = threadIdx.x;
-    const int jrev = blockIdx.x / a.bp;
-    const int pl = blockIdx.x - jrev * a.bp;
-    const int j = a.nd - 1 - jrev;
-    const double period = a.periods[pl];
-    const double dur = a.durations[j];
-    ItemBest* out = a.items + (size_t)pl * a.nd + j;
-    if (!duration_valid(period, dur, a.prm)) {
-        if (tid == 0) {
-            out->dchi2 = -INFINITY;
-            out->depth = 0.0;
-            out->start = -1;
-            out->d = 0;
-            out->evals = 0;
-        }
-        return;
-    }
-    const int64_t n = a.n;
-    const int64_t D = points_in(n, period, dur);
-    const int64_t stride = t0_stride(D, a.prm.dt0);
-    const double* __restrict__ rp = a.rpad + (size_t)pl * a.pstride;
-    const double* __restrict__ wp = VARW ? a.wpad + (size_t)pl * a.pstride : nullptr;
-    const __int128* __restrict__ pf = MEAN ? a.pfx + (size_t)pl * (a.pstride + 1) : nullptr;
-    const double wc = __longlong_as_double((long long)a.misc[kWminBits]);
-    const int64_t limit = n + D;
-    Best best{-INFINITY, 0.0, -1};
-
-    if (stride == 1) {
-        for (int64_t i0 = 0; i0 < n; i0 += kTile) {
-            double acc[kR];
-            double bacc[VARW ? kR : 1];
-#pragma unroll
-            for (int m = 0; m < kR; ++m) acc[m] = 0.0;
-#pragma unroll
-            for (int m = 0; m < (VARW ? kR : 1); ++m) bacc[m] = 0.0;
-            double bsh = 0.0, s1 = 0.0;
-            for (int64_t k0 = 0; k0 < D; k0 += kKC) {
-                const int kc = (int)min((int64_t)kKC, ((D - k0 + kR - 1) / kR) * kR);
-                __syncthreads();
-                for (int kk = tid; kk < kc; kk += kSlideThreads) {
-                    const int64_t k = k0 + kk;
-                    const double sv = (k < D) ? resample(a.tmpl, a.nt, D, k) : 0.0;
-                    s_sh[kk] = sv;
-                    s2_sh[kk] = sv * sv;
-                }
-                const int nx = kTile + kc;
-                for (int e = tid; e < nx; e += kSlideThreads) {
-                    const int64_t g = i0 + k0 + e;
-                    x_sh[xpad(e)] = (g < limit) ? rp[g] : 0.0;
-                    if (VARW) xw_sh[xpad(e)] = (g < limit) ? wp[g] : 0.0;
-                }
-                __syncthreads();
-                const int base = tid * kR;
-                double x[2 * kR];
-                double xw[VARW ? 2 * kR : 1];
-#pragma unroll
-                for (int m = 0; m < kR; ++m) {
-                    x[m] = x_sh[xpad(base) + m];
-                    if (VARW) xw[m] = xw_sh[xpad(base) + m];
-                }
-                for (int kb = 0; kb < kc; kb += kR) {
-                    const int g1 = xpad(base + kb + kR);
-#pragma unroll
-                    for (int m = 0; m < kR; ++m) {
-                        x[kR + m] = x_sh[g1 + m];
-                        if (VARW) xw[kR + m] = xw_sh[g1 + m];
-                    }
-#pragma unroll
-                    for (int uu = 0; uu < kR; ++uu) {
-                        const double sv = s_sh[kb + uu];
-                        const double s2 = s2_sh[kb + uu];
-#pragma unroll
-                        for (int m = 0; m < kR; ++m) acc[m] = fma(x[uu + m], sv, acc[m]);
-                        if (VARW) {
-#pragma unroll
-                            for (int m = 0; m < kR; ++m) bacc[m] = fma(xw[uu + m], s2, bacc[m]);
-                        } else {
-                            bsh = fma(wc, s2, bsh);
-                        }
-                        if (MEAN) s1 = s1 + sv;
-                    }
-#pragma unroll
-                    for (int m = 0; m < kR; ++m) {
-                        x[m] = x[kR + m];
-                        if (VARW) xw[m] = xw[kR + m];
-                    }
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < kR; ++m) {
-                const int64_t i = i0 + (int64_t)tid * kR + m;
-                if (i < n) {
-                    double dchi2, depth;
-                    fit<MEAN>(acc[m], VARW ? bacc[m] : bsh, window_deficit<MEAN>(pf, i, D), s1, dchi2, depth);
-                    consider(best, dchi2, depth, i);
-                }
-            }
-        }
-    } else {
-        // Strided T0 grid: one window per lane at a time, template from LDS.
-        const int64_t nw = (n + stride - 1) / stride;
-        double bsh = 0.0, s1 = 0.0;
-        bool have_b = false;
-        for (int64_t m0 = 0; m0 < nw; m0 += kSlideThreads) {
-            const int64_t m = m0 + tid;
-            const bool active = m < nw;
-            const int64_t i = m * stride;
-            double c = 0.0, bv = 0.0;
-            for (int64_t k0 = 0; k0 < D; k0 += kKC) {
-                const int kc = (int)min((int64_t)kKC, D - k0);
-                __syncthreads();
-                for (int kk = tid; kk < kc; kk += kSlideThreads) {
-                    const double sv = resample(a.tmpl, a.nt, D, k0 + kk);
-                    s_sh[kk] = sv;
-                    s2_sh[kk] = sv * sv;
-                }
-                __syncthreads();
-                if (!have_b) {
-                    for (int kk = 0; kk < kc; ++kk) {
-                        if (!VARW) bsh = fma(wc, s2_sh[kk], bsh);
-                        if (MEAN) s1 = s1 + s_sh[kk];
-                    }
-                }
-                if (active) {
-                    const double* __restrict__ rr = rp + i + k0;
-                    const double* __restrict__ ww = VARW ? wp + i + k0 : nullptr;
-                    for (int kk = 0; kk < kc; ++kk) {
-                        c = fma(rr[kk], s_sh[kk], c);
-                        if (VARW) bv = fma(ww[kk], s2_sh[kk], bv);
-                    }
-                }
-            }
-            have_b = true;
-            if (active) {
-                double dchi2, depth;
-                fit<MEAN>(c, VARW ? bv : bsh, window_deficit<MEAN>(pf, i, D), s1, dchi2, depth);
-                consider(best, dchi2, depth, i);
-            }
-        }
-    }
-
-    // Reduce: largest dchi2, smallest start among equals (first occurrence).
     for (int off = 32; off > 0; off >>= 1) {
-        double od = __shfl_xor(best.dchi2, off);
-        double op = __shfl_xor(best.depth, off);
-        long long oi = __shfl_xor((long long)best.start, off);
-        bool take = (od > best.dchi2) || (od == best.dchi2 && oi >= 0 && (best.start < 0 || oi < best.start));
+        const double od = __shfl_xor(best.dchi2, off);
+        const double op = __shfl_xor(best.depth, off);
+        const long long oi = __shfl_xor((long long)best.start, off);
+        const bool take = (od > best.dchi2) || (od == best.dchi2 && oi >= 0 && (best.start < 0 || oi < best.start));
         if (take) {
             best.dchi2 = od;
             best.depth = op;
@@ -640,12 +638,235 @@ __global__ __launch_bounds__(kSlideThreads) void k_slide(SlideArgs a) {
             if (o.dchi2 > b.dchi2 || (o.dchi2 == b.dchi2 && o.start >= 0 && (b.start < 0 || o.start < b.start)))
                 b = o;
         }
+        ItemBest* out = item_slot(a, it);
         out->dchi2 = b.dchi2;
         out->depth = b.depth;
         out->start = (int32_t)b.start;
-        out->d = (int32_t)D;
-        out->evals = (int32_t)((n + stride - 1) / stride);
+        out->d = (int32_t)it.d;
+        out->evals = (int32_t)evals;
+        if (it.tile == 0) out->ntiles = ntiles;
     }
+}
+
+__device__ __forceinline__ void store_invalid(const SlideArgs& a, const ItemInfo& it) {
+    if (threadIdx.x == 0 && it.tile == 0) {
+        ItemBest* out = item_slot(a, it);
+        out->dchi2 = -INFINITY;
+        out->depth = 0.0;
+        out->start = -1;
+        out->d = 0;
+        out->evals = 0;
+        out->ntiles = 1;
+    }
+}
+
+// 16 template steps on 16 windows: window m at step u reads lo[u+m] (or
+// hi[u+m-16]); one fused multiply-add per step in ascending template order.
+// SQ squares the template value (the b = sum w s^2 sums of varying weights).
+template <typename T, bool SQ>
+__device__ __forceinline__ void block16(T (&acc)[kR], const T (&lo)[kR], const T (&hi)[kR], cptr<T> t) {
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+        const T sv = SQ ? t[u] * t[u] : t[u];
+#pragma unroll
+        for (int m = 0; m < kR; ++m) acc[m] = fma((u + m < kR) ? lo[u + m] : hi[u + m - kR], sv, acc[m]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ld16(T (&x)[kR], const T* p) {
+#pragma unroll
+    for (int m = 0; m < kR; ++m) x[m] = p[m];
+}
+
+// Correlation of the 16 windows of this lane over one staged chunk of kc
+// template points.  FP64 accumulates straight into acc; FP32 accumulates
+// each 32-point block in float and adds it to the FP64 accumulator.
+template <typename T, bool SQ>
+__device__ __forceinline__ void chunk_correlate(double (&acc)[kR], const T* xs, int base, int kc, cptr<T> t) {
+    T xa[kR], xb[kR];
+    ld16(xa, xs + xpad<T>(base));
+    for (int kb = 0; kb < kc; kb += 2 * kR) {
+        if constexpr (sizeof(T) == 8) {
+            ld16(xb, xs + xpad<T>(base + kb + kR));
+            block16<T, SQ>(acc, xa, xb, t + kb);
+            ld16(xa, xs + xpad<T>(base + kb + 2 * kR));
+            block16<T, SQ>(acc, xb, xa, t + kb + kR);
+        } else {
+            T a32[kR];
+#pragma unroll
+            for (int m = 0; m < kR; ++m) a32[m] = (T)0;
+            ld16(xb, xs + xpad<T>(base + kb + kR));
+            block16<T, SQ>(a32, xa, xb, t + kb);
+            ld16(xa, xs + xpad<T>(base + kb + 2 * kR));
+            block16<T, SQ>(a32, xb, xa, t + kb + kR);
+#pragma unroll
+            for (int m = 0; m < kR; ++m) acc[m] += (double)a32[m];
+        }
+    }
+}
+
+// Every T0 offset (stride 1): each lane owns 16 consecutive windows; their
+// correlation sums advance together over a padded LDS copy of the curve,
+// with the template streamed from the table into scalar registers.
+template <typename T, bool VARW, bool MEAN>
+__global__ __launch_bounds__(kSlideThreads) void k_slide_unit(SlideArgs a) {
+    __shared__ T x_sh[xpad<T>(kXs)];
+    __shared__ T xw_sh[VARW ? xpad<T>(kXs) : 1];
+    __shared__ Best red[kSlideThreads / 64];
+    const ItemInfo it = item_info(a, a.ntiles);
+    if (!it.valid) {
+        store_invalid(a, it);
+        return;
+    }
+    if (it.stride != 1) return;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int64_t n = a.n, D = it.d;
+    const T* __restrict__ rp = (const T*)a.rpad + (size_t)it.pl * a.pstride;
+    const T* __restrict__ wp = VARW ? (const T*)a.wpad + (size_t)it.pl * a.pstride : nullptr;
+    const void* pf = MEAN ? (const void*)((const char*)a.pfx + (size_t)it.pl * (a.pstride + 1) *
+                                          (sizeof(T) == 8 ? sizeof(__int128) : sizeof(float2)))
+                          : nullptr;
+    const cptr<T> trow = (cptr<T>)((const T*)a.table + trow_off(D));
+    const double bconst = VARW ? 0.0 : a.bsum[D];
+    const double s1 = MEAN ? a.s1sum[D] : 0.0;
+    const int64_t limit = n + D;
+    const int64_t dpad = rup32(D);
+    const int base = tid * kR;
+    const int64_t i0 = (int64_t)it.tile * kTile;
+    Best best{-INFINITY, 0.0, -1};
+
+    const bool busy = i0 + (int64_t)wave * 64 * kR < n;     // wave has at least one window
+    double acc[kR], bacc[VARW ? kR : 1];
+#pragma unroll
+    for (int m = 0; m < kR; ++m) acc[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < (VARW ? kR : 1); ++m) bacc[m] = 0.0;
+    for (int64_t k0 = 0; k0 < dpad; k0 += kKC) {
+        const int kc = (int)min((int64_t)kKC, dpad - k0);
+        if (k0 > 0) __syncthreads();
+        const int nx = kTile + kc + kR;
+        for (int e = tid; e < nx; e += kSlideThreads) {
+            const int64_t g = i0 + k0 + e;
+            x_sh[xpad<T>(e)] = (g < limit) ? rp[g] : (T)0;
+            if (VARW) xw_sh[xpad<T>(e)] = (g < limit) ? wp[g] : (T)0;
+        }
+        __syncthreads();
+        if (!busy) continue;
+        chunk_correlate<T, false>(acc, x_sh, base, kc, trow + k0);
+        if constexpr (VARW) chunk_correlate<T, true>(bacc, xw_sh, base, kc, trow + k0);
+    }
+#pragma unroll
+    for (int m = 0; m < kR; ++m) {
+        const int64_t i = i0 + base + m;
+        if (i < n) {
+            double dchi2, depth;
+            fit<MEAN>(acc[m], VARW ? bacc[m] : bconst, window_deficit<T, MEAN>(pf, i, D), s1, dchi2, depth);
+            consider(best, dchi2, depth, i);
+        }
+    }
+    store_best(best, a, it, red, min((int64_t)kTile, n - i0), a.ntiles);
+}
+
+// Strided T0 grid (stride >= 2): one window per lane, each wave working on
+// its own 64 windows through a wave-private LDS tile.  Small strides stage
+// the contiguous span the 64 windows cover (each point read once); large
+// strides stage each window's next 32 points as a transposed 64 x 32 tile
+// (coalesced reads of 32-point runs).  The template is a uniform stream.
+constexpr int kSTC = 32;                            // template points per tile step (transposed mode)
+constexpr int kSPitch = kSTC + 1;
+constexpr int kSTile = 64 * kSPitch;                // elements per wave tile
+
+template <typename T, bool VARW, bool MEAN>
+__global__ __launch_bounds__(kSlideThreads) void k_slide_strided(SlideArgs a) {
+    __shared__ T tile[kSlideThreads / 64][kSTile];
+    __shared__ T tilew[VARW ? kSlideThreads / 64 : 1][VARW ? kSTile : 1];
+    __shared__ Best red[kSlideThreads / 64];
+    const ItemInfo it = item_info(a, 1);
+    if (!it.valid || it.stride == 1) return;     // the unit-stride kernel writes those items
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t n = a.n, D = it.d, s = it.stride;
+    const int64_t nw = (n + s - 1) / s;
+    const T* __restrict__ rp = (const T*)a.rpad + (size_t)it.pl * a.pstride;
+    const T* __restrict__ wp = VARW ? (const T*)a.wpad + (size_t)it.pl * a.pstride : nullptr;
+    const void* pf = MEAN ? (const void*)((const char*)a.pfx + (size_t)it.pl * (a.pstride + 1) *
+                                          (sizeof(T) == 8 ? sizeof(__int128) : sizeof(float2)))
+                          : nullptr;
+    const cptr<T> trow = (cptr<T>)((const T*)a.table + trow_off(D));
+    const double bconst = VARW ? 0.0 : a.bsum[D];
+    const double s1 = MEAN ? a.s1sum[D] : 0.0;
+    const int64_t limit = n + D;
+    const int64_t dpad = rup32(D);
+    T* tl = tile[wave];
+    T* tw = VARW ? tilew[wave] : nullptr;
+    // Contiguous mode: the 64 windows of a group span 63 s + TCu points.
+    const int64_t tcu = (kSTile - 63 * s) & ~(int64_t)31;
+    const bool contiguous = tcu >= 32;
+    const int64_t tc = contiguous ? tcu : kSTC;
+    Best best{-INFINITY, 0.0, -1};
+
+    for (int64_t g0 = (int64_t)wave * 64; g0 < nw; g0 += kSlideThreads) {
+        const int64_t m = g0 + lane;
+        const bool active = m < nw;
+        const int64_t i = m * s;
+        const int64_t ibase = g0 * s;
+        double c = 0.0, bv = 0.0;
+        for (int64_t k0 = 0; k0 < dpad; k0 += tc) {
+            const int kc = (int)min(tc, dpad - k0);
+            if (contiguous) {
+                const int64_t span = 63 * s + kc;
+                for (int64_t e = lane; e < span; e += 64) {
+                    const int64_t gsrc = ibase + k0 + e;
+                    tl[e] = (gsrc < limit) ? rp[gsrc] : (T)0;
+                    if (VARW) tw[e] = (gsrc < limit) ? wp[gsrc] : (T)0;
+                }
+            } else {
+                const int e = lane & 31;
+                for (int r = 0; r < 32; ++r) {
+                    const int seg = 2 * r + (lane >> 5);
+                    const int64_t mm = g0 + seg;
+                    const int64_t gsrc = mm * s + k0 + e;
+                    const bool ok = mm < nw && gsrc < limit;
+                    tl[seg * kSPitch + e] = ok ? rp[gsrc] : (T)0;
+                    if (VARW) tw[seg * kSPitch + e] = ok ? wp[gsrc] : (T)0;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const T* xl = contiguous ? tl + lane * s : tl + lane * kSPitch;
+            const T* xw = VARW ? (contiguous ? tw + lane * s : tw + lane * kSPitch) : nullptr;
+            const cptr<T> t = trow + k0;
+            for (int kb = 0; kb < kc; kb += kSTC) {
+                T cb = (sizeof(T) == 8) ? (T)c : (T)0;
+                T bb = (sizeof(T) == 8) ? (T)bv : (T)0;
+#pragma unroll
+                for (int kk = 0; kk < kSTC; ++kk) {
+                    const T sv = t[kb + kk];
+                    cb = fma(xl[kb + kk], sv, cb);
+                    if (VARW) bb = fma(xw[kb + kk], sv * sv, bb);
+                }
+                if constexpr (sizeof(T) == 8) {
+                    c = cb;
+                    bv = bb;
+                } else {
+                    c += (double)cb;
+                    bv += (double)bb;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (active) {
+            double dchi2, depth;
+            fit<MEAN>(c, VARW ? bv : bconst, window_deficit<T, MEAN>(pf, i, D), s1, dchi2, depth);
+            consider(best, dchi2, depth, i);
+        }
+    }
+    store_best(best, a, it, red, nw, 1);
 }
 
 // ------------------------------------------------------------------------
@@ -658,6 +879,7 @@ struct ReduceArgs {
     int32_t bp;
     int32_t nd;
     const ItemBest* items;
+    int32_t ntiles;
     const uint64_t* keys_a;
     const uint64_t* misc;
     uint64_t* misc_rw;
@@ -674,20 +896,23 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
     if (pl < a.bp) {
         const double chi2_0 = __longlong_as_double((long long)a.misc[kChi2Null]);
         const double tmin = from_ordered(a.misc[kTminOrd]);
-        const ItemBest* it = a.items + (size_t)pl * a.nd;
         double best = -INFINITY, bdepth = 0.0;
         int bj = -1, bi = -1, bd = 0;
         for (int j = 0; j < a.nd; ++j) {
-            const ItemBest b = it[j];
-            if (b.start < 0) continue;
-            evals += (uint64_t)b.evals;
-            macs += (uint64_t)b.evals * (uint64_t)b.d;
-            if (b.dchi2 > best) {
-                best = b.dchi2;
-                bdepth = b.depth;
-                bj = j;
-                bi = b.start;
-                bd = b.d;
+            const ItemBest* slots = a.items + ((size_t)pl * a.nd + j) * a.ntiles;
+            const int nt = min(max(slots[0].ntiles, 0), a.ntiles);
+            for (int t = 0; t < nt; ++t) {
+                const ItemBest b = slots[t];
+                if (b.start < 0) continue;
+                evals += (uint64_t)b.evals;
+                macs += (uint64_t)b.evals * (uint64_t)b.d;
+                if (b.dchi2 > best) {
+                    best = b.dchi2;
+                    bdepth = b.depth;
+                    bj = j;
+                    bi = b.start;
+                    bd = b.d;
+                }
             }
         }
         if (bj < 0) {
@@ -933,9 +1158,10 @@ hipError_t run_sde(gtls_ctx* ctx, const double* chi2, int32_t n, int32_t window,
 namespace {
 
 struct Plan {
-    int64_t n, pstride;
-    int32_t bp;
-    bool varw, mean;
+    int64_t n, pstride, dcap;
+    int32_t bp, ntiles;
+    bool varw, mean, f32;
+    size_t esize, psize;     // bytes per padded-curve element and per prefix element
     size_t off_a, off_b, off_r, off_w, off_pf, off_items, per_batch;
 };
 
@@ -944,16 +1170,24 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     p.n = n;
     p.varw = varw;
     p.mean = prm.depth_mode == GTLS_DEPTH_MEAN;
+    p.f32 = prm.precision == GTLS_FP32C;
+    p.esize = p.f32 ? sizeof(float) : sizeof(double);
+    p.psize = p.f32 ? sizeof(float2) : sizeof(__int128);
     int64_t dcap = (int64_t)std::floor((double)n * prm.q_cap + 0.5);
     dcap = std::max<int64_t>(1, std::min<int64_t>(n, dcap));
+    p.dcap = dcap;
+    p.ntiles = (int32_t)((n + kTile - 1) / kTile);
     p.pstride = ((n + dcap + 63) / 64) * 64;
-    size_t per = 2 * sizeof(uint64_t) * (size_t)n + sizeof(double) * (size_t)p.pstride +
-                 (varw ? sizeof(double) * (size_t)p.pstride : 0) +
-                 (p.mean ? sizeof(__int128) * (size_t)(p.pstride + 1) : 0) + sizeof(ItemBest) * (size_t)nd + 1024;
-    const size_t budget = (size_t)8 << 30;
+    size_t per = 2 * sizeof(uint64_t) * (size_t)n + p.esize * (size_t)p.pstride +
+                 (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
+                 sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles + 1024;
+    const size_t budget = (size_t)24 << 30;
     int64_t bp = (int64_t)(budget / per);
     bp = std::max<int64_t>(1, std::min<int64_t>(bp, 8192));
     bp = std::min<int64_t>(bp, n_periods);
+    // one-dimensional grids of bp * nd * ntiles work units
+    const int64_t units = std::max<int64_t>(1, (int64_t)nd * p.ntiles);
+    bp = std::max<int64_t>(1, std::min<int64_t>(bp, 0x7fffffffLL / units));
     p.bp = (int32_t)bp;
     size_t o = 0;
     p.off_a = o;
@@ -961,15 +1195,33 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     p.off_b = o;
     o = align256(o + sizeof(uint64_t) * (size_t)n * bp);
     p.off_r = o;
-    o = align256(o + sizeof(double) * (size_t)p.pstride * bp);
+    o = align256(o + p.esize * (size_t)p.pstride * bp);
     p.off_w = o;
-    if (varw) o = align256(o + sizeof(double) * (size_t)p.pstride * bp);
+    if (varw) o = align256(o + p.esize * (size_t)p.pstride * bp);
     p.off_pf = o;
-    if (p.mean) o = align256(o + sizeof(__int128) * (size_t)(p.pstride + 1) * bp);
+    if (p.mean) o = align256(o + p.psize * (size_t)(p.pstride + 1) * bp);
     p.off_items = o;
-    o = align256(o + sizeof(ItemBest) * (size_t)nd * bp);
+    o = align256(o + sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles * bp);
     p.per_batch = o;
     return p;
+}
+
+template <typename T, bool VARW, bool MEAN>
+void launch_slides(const SlideArgs& la, unsigned grid, unsigned grid_items, bool strided, hipStream_t s) {
+    k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
+    if (strided) k_slide_strided<T, VARW, MEAN><<<grid_items, kSlideThreads, 0, s>>>(la);
+}
+
+template <typename T>
+void launch_slides(const SlideArgs& la, unsigned grid, unsigned grid_items, bool strided, bool varw, bool mean,
+                   hipStream_t s) {
+    if (varw) {
+        if (mean) launch_slides<T, true, true>(la, grid, grid_items, strided, s);
+        else launch_slides<T, true, false>(la, grid, grid_items, strided, s);
+    } else {
+        if (mean) launch_slides<T, false, true>(la, grid, grid_items, strided, s);
+        else launch_slides<T, false, false>(la, grid, grid_items, strided, s);
+    }
 }
 
 }  // namespace
@@ -1000,38 +1252,49 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     const bool varw = hmisc[kWminBits] != hmisc[kWmaxBits];
 
     const Plan pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw);
+    // Template rows for every D in [1, dcap] and the per-D sums.
+    const size_t tab_elems = (size_t)trow_off(pl.dcap + 1);
+    const size_t off_bsum = align256(pl.esize * tab_elems), off_s1 = align256(off_bsum + 8 * (size_t)(pl.dcap + 1));
+    e = ensure(ctx, ctx->table, align256(off_s1 + 8 * (size_t)(pl.dcap + 1)));
+    if (e != hipSuccess) return e;
+    void* table = ctx->table.ptr;
+    double* bsum = (double*)((char*)ctx->table.ptr + off_bsum);
+    double* s1sum = (double*)((char*)ctx->table.ptr + off_s1);
+    {
+        StageTimer tm(ctx, kStagePrep);
+        if (pl.f32) k_tmpl_table<float><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, (float*)table);
+        else k_tmpl_table<double><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, (double*)table);
+        k_tmpl_sums<<<(unsigned)((pl.dcap + 63) / 64), 64, 0, s>>>(a.tmpl, a.n_tmpl, pl.dcap, misc, bsum, s1sum);
+    }
     e = ensure(ctx, ctx->batch, pl.per_batch);
     if (e != hipSuccess) return e;
     char* bb = (char*)ctx->batch.ptr;
     uint64_t* keys_a = (uint64_t*)(bb + pl.off_a);
     uint64_t* keys_b = (uint64_t*)(bb + pl.off_b);
-    double* rpad = (double*)(bb + pl.off_r);
-    double* wpad = varw ? (double*)(bb + pl.off_w) : nullptr;
-    __int128* pfx = pl.mean ? (__int128*)(bb + pl.off_pf) : nullptr;
+    void* rpad = bb + pl.off_r;
+    void* wpad = varw ? (void*)(bb + pl.off_w) : nullptr;
+    void* pfx = pl.mean ? (void*)(bb + pl.off_pf) : nullptr;
     ItemBest* items = (ItemBest*)(bb + pl.off_items);
+    const bool strided = a.prm.dt0 > 0.0;
 
     for (int32_t p0 = 0; p0 < a.n_periods; p0 += pl.bp) {
         const int32_t bp = std::min(pl.bp, a.n_periods - p0);
         SortArgs sa{a.t, r, w, u, n, a.periods + p0, a.durations, a.n_durations, a.prm, keys_a, keys_b,
-                    rpad, wpad, pfx, pl.pstride, nullptr};
+                    rpad, wpad, pfx, pl.pstride, nullptr, pl.f32 ? 1 : 0};
         {
             StageTimer tm(ctx, kStageSort);
             k_fold_sort<<<bp, kSortThreads, 0, s>>>(sa);
         }
-        SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.tmpl, a.n_tmpl, a.prm,
-                     rpad, wpad, pfx, pl.pstride, misc, items};
-        const unsigned grid = (unsigned)bp * (unsigned)a.n_durations;
+        SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.prm, rpad, wpad, pfx, pl.pstride,
+                     misc, table, bsum, s1sum, items, pl.ntiles};
+        const unsigned grid = (unsigned)bp * (unsigned)a.n_durations * (unsigned)pl.ntiles;
+        const unsigned grid_items = (unsigned)bp * (unsigned)a.n_durations;
         {
             StageTimer tm(ctx, kStageSlide);
-            if (varw) {
-                if (pl.mean) k_slide<true, true><<<grid, kSlideThreads, 0, s>>>(la);
-                else k_slide<true, false><<<grid, kSlideThreads, 0, s>>>(la);
-            } else {
-                if (pl.mean) k_slide<false, true><<<grid, kSlideThreads, 0, s>>>(la);
-                else k_slide<false, false><<<grid, kSlideThreads, 0, s>>>(la);
-            }
+            if (pl.f32) launch_slides<float>(la, grid, grid_items, strided, varw, pl.mean, s);
+            else launch_slides<double>(la, grid, grid_items, strided, varw, pl.mean, s);
         }
-        ReduceArgs ra{a.t, n, a.periods + p0, bp, a.n_durations, items, keys_a, misc, misc,
+        ReduceArgs ra{a.t, n, a.periods + p0, bp, a.n_durations, items, pl.ntiles, keys_a, misc, misc,
                       a.chi2 + p0, a.best_dur + p0, a.best_start + p0, a.depth + p0, a.t0 + p0};
         {
             StageTimer tm(ctx, kStageReduce);
@@ -1059,13 +1322,11 @@ hipError_t run_fold_sort(gtls_ctx* ctx, const double* t, int64_t n, const double
     e = ensure(ctx, ctx->batch, pl.per_batch);
     if (e != hipSuccess) return e;
     char* bb = (char*)ctx->batch.ptr;
-    static const double no_duration = 0.0;
-    (void)no_duration;
     for (int32_t p0 = 0; p0 < n_periods; p0 += pl.bp) {
         const int32_t bp = std::min(pl.bp, n_periods - p0);
         SortArgs sa{t, r, r, u, n, periods + p0, periods, 0, prm, (uint64_t*)(bb + pl.off_a),
-                    (uint64_t*)(bb + pl.off_b), (double*)(bb + pl.off_r), nullptr, nullptr, pl.pstride,
-                    perm + (size_t)p0 * n};
+                    (uint64_t*)(bb + pl.off_b), bb + pl.off_r, nullptr, nullptr, pl.pstride,
+                    perm + (size_t)p0 * n, 0};
         k_fold_sort<<<bp, kSortThreads, 0, s>>>(sa);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -97,10 +97,13 @@ def test_sde_kernel_matches_oracle(ctx, oracle):
     (6, 1200, dict(shuffle=True)),
     (7, 64, dict(envelope=0, q_cap=1.0)),
     (8, 9000, dict(dt0=0.02)),
+    (13, 30011, dict(dt0=0.1, cadence=0.002)),
+    (14, 24000, dict(dt0=0.5, cadence=0.002, varying_dy=True)),
+    (15, 20000, dict(dt0=0.3, cadence=0.002, depth_mode=1)),
 ])
 def test_random_curves_match_oracle(ctx, oracle, seed, n, kw):
     kw = dict(kw)
-    gen_kw = {k: kw.pop(k) for k in ("varying_dy", "shuffle") if k in kw}
+    gen_kw = {k: kw.pop(k) for k in ("varying_dy", "shuffle", "cadence") if k in kw}
     c = synth.curve_random(seed, n=n, inject=True, **gen_kw)
     span = c["t"].max() - c["t"].min()
     periods = oracle.period_grid_ofir(span, 2.0, pmin_days=0.5, pmax_days=max(0.6, span / 2))
@@ -133,6 +136,79 @@ def test_kepler_90d_full_grid(ctx, oracle):
     assert np.array_equal(res.sde, sde)
     assert res.best_period == best
     assert abs(periods[best] - 7.3) < 0.01
+
+
+def _sampled(oracle, c, periods, durs, tm, idx, **kw):
+    return oracle.tls_search(c["t"], c["y"], c["dy"], periods[idx], durs, tm, threads=THREADS, **kw)
+
+
+def _compare_rows(res, ref, idx, label):
+    assert np.allclose(res.chi2[idx], ref.chi2, rtol=RTOL, atol=0), label
+    assert np.array_equal(res.best_dur[idx], ref.best_dur), label
+    assert np.array_equal(res.best_start[idx], ref.best_start), label
+    assert np.allclose(res.depth[idx], ref.depth, rtol=RTOL, atol=1e-300), label
+    assert np.allclose(res.t0[idx], ref.t0, rtol=RTOL, atol=0), label
+
+
+def test_kepler_3000d_full_grid_sampled(ctx, oracle):
+    """The 3000-day workload over its whole Ofir grid (418,590 periods,
+    20 durations) at dt0 = 0.1; the oracle recomputes a seeded sample of
+    periods plus the neighbourhood of the injected and the best period."""
+    c = synth.curve_3000d()
+    span = c["t"][-1] - c["t"][0]
+    periods = oracle.period_grid_ofir(span, 3.0, pmin_days=0.5, pmax_days=1500.0)
+    durs = oracle.duration_grid(0.5, 1500.0, 20)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    _say("kepler_3000d full grid dt0=0.1", len(periods), len(c["t"]))
+    res, prm = _search_both(ctx, c, periods, durs, tm, dt0=0.1)
+    inj = int(np.argmin(np.abs(periods - 365.0)))
+    g = synth.rng(77)
+    idx = np.unique(np.r_[g.choice(len(periods), 40, replace=False), inj - 2, inj - 1, inj, inj + 1, inj + 2,
+                          res.best_period, 0, len(periods) - 1])
+    ref = _sampled(oracle, c, periods, durs, tm, idx, dt0=0.1)
+    _compare_rows(res, ref, idx, "kepler_3000d")
+    assert abs(periods[res.best_period] / 365.0 - 1) < 0.01
+    # periodogram statistics at full size, from the GPU chi2 (properties)
+    sr = res.chi2.min() / res.chi2
+    assert np.array_equal(res.sr, sr)
+    assert np.argmax(res.sde) == res.best_period
+
+
+def test_kepler_3000d_every_offset_subset(ctx, oracle):
+    """Every T0 offset on the 3000-day curve, for a seeded subset of its
+    grid (periods are independent, so a subset is an exact slice)."""
+    c = synth.curve_3000d()
+    span = c["t"][-1] - c["t"][0]
+    periods = oracle.period_grid_ofir(span, 3.0, pmin_days=0.5, pmax_days=1500.0)
+    g = synth.rng(78)
+    inj = int(np.argmin(np.abs(periods - 365.0)))
+    idx = np.unique(np.r_[g.choice(len(periods), 10, replace=False), inj])
+    durs = oracle.duration_grid(0.5, 1500.0, 20)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    _say("kepler_3000d every offset subset", len(idx))
+    res, prm = _search_both(ctx, c, periods[idx], durs, tm)
+    ref = _sampled(oracle, c, periods, durs, tm, idx)
+    _compare_rows(res, ref, np.arange(len(idx)), "kepler_3000d dt0=0")
+
+
+def test_tess_bjd_times_every_offset_subset(ctx, oracle):
+    """350 days of 2-min cadence at BJD-scale times (t ~ 2.46e6): the fold
+    must keep phase order exact at large |t| / P."""
+    c = synth.curve_tess()
+    span = c["t"][-1] - c["t"][0]
+    periods = oracle.period_grid_ofir(span, 3.0, pmax_days=175.0)
+    durs = oracle.duration_grid(periods[0], periods[-1], 20)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    g = synth.rng(79)
+    inj = int(np.argmin(np.abs(periods - 0.7)))
+    idx = np.unique(np.r_[g.choice(len(periods), 6, replace=False), inj])
+    _say("tess every offset subset", len(idx), len(c["t"]))
+    res, prm = _search_both(ctx, c, periods[idx], durs, tm)
+    ref = _sampled(oracle, c, periods, durs, tm, idx)
+    _compare_rows(res, ref, np.arange(len(idx)), "tess")
+    got = gtls.tls_fold_sort(ctx, c["t"], periods[idx[:3]])
+    for k in range(3):
+        assert np.array_equal(got[k], oracle.fold_sort(c["t"], periods[idx[k]]))
 
 
 def test_edge_cases(ctx, oracle):
