@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--workload", default="kepler_3000d", choices=["kepler_3000d", "kepler_90d", "tess_13sector"])
     ap.add_argument("--dt0", type=float, default=0.1)
     ap.add_argument("--depth-mode", choices=["wls", "mean"], default="wls")
+    ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="periods the oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -91,7 +92,8 @@ def main():
     from paper_2607_00348_amd import gtls
 
     c, periods, durs, tm = workload(args.workload)
-    prm = gtls.gtls_params_default(dt0=args.dt0, depth_mode=(1 if args.depth_mode == "mean" else 0))
+    prm = gtls.gtls_params_default(dt0=args.dt0, depth_mode=(1 if args.depth_mode == "mean" else 0),
+                                   precision=(gtls.GTLS_FP32C if args.precision == "fp32c" else gtls.GTLS_FP64))
     dev = torch.device("cuda:0")
     f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     t_d, y_d, dy_d = f64(c["t"]), f64(c["y"]), f64(c["dy"])
@@ -160,10 +162,10 @@ def main():
 
     line = {"metric": METRIC, "value": evals_per_s, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
             "config": {"workload": args.workload, "n_points": int(len(c["t"])), "n_periods": int(npd),
                        "n_durations": int(len(durs)), "dt0": args.dt0, "depth_mode": args.depth_mode,
-                       "precision": "fp64"},
+                       "precision": args.precision},
             "light_curves_per_hour": 3600.0 / (ms_per_step * 1e-3),
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
             "roofline": roof}

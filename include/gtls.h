@@ -171,6 +171,43 @@ gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux
                            int32_t *best_start, double *depth, double *t0, double *sr,
                            double *sde_raw, double *sde, gtls_summary *summary);
 
+/* Batched survey: many light curves searched in one persistent launch over
+ * (curve, period) work items (Sect. 2.3-2.4 per curve).
+ *   offsets [n_curves + 1], host: curve c owns points
+ *     [offsets[c], offsets[c + 1]) of time/flux/dy; offsets[0] = 0, each
+ *     curve has 3 <= n_c < 2^31 points (same rules as tls_search).
+ *   period_offsets [n_curves + 1], host: curve c's grid is
+ *     periods[period_offsets[c] .. period_offsets[c + 1]), at least one
+ *     period, strictly increasing; period_offsets[0] = 0.
+ *   duration_grid, tmpl, params: shared by all curves.
+ * Per-period outputs use the same CSR layout as periods (length
+ * period_offsets[n_curves]); best_period in summaries[c] indexes curve c's
+ * grid.  Each curve's results equal those of tls_search on that curve.
+ * Host arrays; any per-period output may be NULL; summaries may be NULL.
+ * Synchronous. */
+gtls_status tls_search_batch(gtls_ctx *ctx, const int64_t *offsets, const double *time,
+                             const double *flux, const double *dy, int32_t n_curves,
+                             const int64_t *period_offsets, const double *periods,
+                             const double *duration_grid, int32_t n_durations,
+                             const double *tmpl, int32_t n_tmpl, const gtls_params *params,
+                             double *chi2, int32_t *best_dur, int32_t *best_start, double *depth,
+                             double *t0, double *sde, gtls_summary *summaries);
+
+/* tls_search_batch on device arrays: offsets and period_offsets stay host
+ * arrays; every other array is a device pointer and all outputs (chi2,
+ * best_dur, best_start, depth, t0, sr, sde_raw, sde, summaries) must be
+ * non-NULL.  The kernels after the per-curve preparation run as one captured
+ * HIP graph that is replayed while the arguments stay the same.  Returns
+ * after enqueueing (call gtls_sync). */
+gtls_status tls_search_batch_dev(gtls_ctx *ctx, const int64_t *offsets, const double *time,
+                                 const double *flux, const double *dy, int32_t n_curves,
+                                 const int64_t *period_offsets, const double *periods,
+                                 const double *duration_grid, int32_t n_durations,
+                                 const double *tmpl, int32_t n_tmpl, const gtls_params *params,
+                                 double *chi2, int32_t *best_dur, int32_t *best_start,
+                                 double *depth, double *t0, double *sr, double *sde_raw,
+                                 double *sde, gtls_summary *summaries);
+
 /* Fold and phase-sort only (Sect. 2.3.1): perm[k * n + i] is the input index
  * of the i-th point in phase order at periods[k]; ties in phase keep input
  * order.  Host arrays; perm has n_periods * n entries. */

@@ -125,7 +125,9 @@ void gtls_destroy(gtls_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (gtls::DeviceBuffer* b : {&ctx->curve, &ctx->batch, &ctx->io, &ctx->sde_tmp, &ctx->table})
+    if (ctx->bcache.exec) (void)hipGraphExecDestroy(ctx->bcache.exec);
+    for (gtls::DeviceBuffer* b : {&ctx->curve, &ctx->batch, &ctx->io, &ctx->sde_tmp, &ctx->table, &ctx->bcurve,
+                                  &ctx->bscratch})
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto& p : ctx->pending) {
         ctx->event_pool.push_back(p.start);
@@ -266,6 +268,110 @@ gtls_status tls_search(gtls_ctx* ctx, const double* time, const double* flux, co
     out->n_evals = sum.n_evals;
     out->n_macs = sum.n_macs;
     if (sum.best_period < 0) return fail(ctx, GTLS_EINTERNAL, "no best period produced");
+    return GTLS_OK;
+}
+
+static gtls_status check_batch_sizes(gtls_ctx* ctx, const int64_t* offsets, int32_t nc, const int64_t* poff,
+                                     int32_t nd, int32_t nt) {
+    if (!offsets || !poff) return fail(ctx, GTLS_EINVAL, "null offsets");
+    if (nc < 1) return fail(ctx, GTLS_EINVAL, "n_curves must be >= 1");
+    if (nd < 1 || nd > 64) return fail(ctx, GTLS_EINVAL, "batched search takes 1..64 durations");
+    if (nt < 2) return fail(ctx, GTLS_EINVAL, "n_tmpl must be >= 2");
+    if (offsets[0] != 0 || poff[0] != 0) return fail(ctx, GTLS_EINVAL, "offsets must start at 0");
+    for (int32_t c = 0; c < nc; ++c) {
+        const int64_t n = offsets[c + 1] - offsets[c];
+        if (n < 3 || n > 0x7fffffff) return fail(ctx, GTLS_EINVAL, "each curve needs 3 <= n < 2^31 points");
+        if (poff[c + 1] - poff[c] < 1) return fail(ctx, GTLS_EINVAL, "each curve needs at least one period");
+    }
+    if (poff[nc] > 0x7fffffff) return fail(ctx, GTLS_EINVAL, "too many periods in one batch");
+    return GTLS_OK;
+}
+
+gtls_status tls_search_batch_dev(gtls_ctx* ctx, const int64_t* offsets, const double* time, const double* flux,
+                                 const double* dy, int32_t n_curves, const int64_t* period_offsets,
+                                 const double* periods, const double* duration_grid, int32_t n_durations,
+                                 const double* tmpl, int32_t n_tmpl, const gtls_params* params, double* chi2,
+                                 int32_t* best_dur, int32_t* best_start, double* depth, double* t0, double* sr,
+                                 double* sde_raw, double* sde, gtls_summary* summaries) {
+    if (!ctx) return GTLS_EINVAL;
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    gtls_status st = check_batch_sizes(ctx, offsets, n_curves, period_offsets, n_durations, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if ((st = check_params(ctx, prm)) != GTLS_OK) return st;
+    if (!time || !flux || !dy || !periods || !duration_grid || !tmpl || !chi2 || !best_dur || !best_start ||
+        !depth || !t0 || !sr || !sde_raw || !sde || !summaries)
+        return fail(ctx, GTLS_EINVAL, "null device pointer");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    gtls::BatchArgsHost a{offsets, period_offsets, n_curves, time, flux, dy, periods, duration_grid, n_durations,
+                          tmpl, n_tmpl, prm, chi2, best_dur, best_start, depth, t0, sr, sde_raw, sde, summaries};
+    e = gtls::run_search_batch(ctx, a);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched search");
+    return GTLS_OK;
+}
+
+gtls_status tls_search_batch(gtls_ctx* ctx, const int64_t* offsets, const double* time, const double* flux,
+                             const double* dy, int32_t n_curves, const int64_t* period_offsets, const double* periods,
+                             const double* duration_grid, int32_t n_durations, const double* tmpl, int32_t n_tmpl,
+                             const gtls_params* params, double* chi2, int32_t* best_dur, int32_t* best_start,
+                             double* depth, double* t0, double* sde, gtls_summary* summaries) {
+    if (!ctx) return GTLS_EINVAL;
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    gtls_status st = check_batch_sizes(ctx, offsets, n_curves, period_offsets, n_durations, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if ((st = check_params(ctx, prm)) != GTLS_OK) return st;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        const int64_t o = offsets[c], po = period_offsets[c];
+        st = check_host_data(ctx, time + o, flux + o, dy + o, offsets[c + 1] - o, periods + po,
+                             (int32_t)(period_offsets[c + 1] - po), duration_grid, n_durations, tmpl, n_tmpl);
+        if (st != GTLS_OK) return st;
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    const size_t npts = (size_t)offsets[n_curves], np = (size_t)period_offsets[n_curves], nc = (size_t)n_curves;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t o_t = take(8 * npts), o_y = take(8 * npts), o_dy = take(8 * npts), o_p = take(8 * np),
+                 o_d = take(8 * (size_t)n_durations), o_tm = take(8 * (size_t)n_tmpl), o_chi2 = take(8 * np),
+                 o_bd = take(4 * np), o_bs = take(4 * np), o_dep = take(8 * np), o_t0 = take(8 * np),
+                 o_sr = take(8 * np), o_raw = take(8 * np), o_sde = take(8 * np),
+                 o_sum = take(sizeof(gtls_summary) * nc);
+    e = gtls::ensure(ctx, ctx->io, o);
+    if (e != hipSuccess) return hip_fail(ctx, e, "device buffers");
+    char* b = (char*)ctx->io.ptr;
+    hipStream_t s = ctx->stream;
+    struct Up { size_t off; const void* src; size_t bytes; } ups[] = {
+        {o_t, time, 8 * npts}, {o_y, flux, 8 * npts}, {o_dy, dy, 8 * npts}, {o_p, periods, 8 * np},
+        {o_d, duration_grid, 8 * (size_t)n_durations}, {o_tm, tmpl, 8 * (size_t)n_tmpl}};
+    for (const Up& u : ups) {
+        e = hipMemcpyAsync(b + u.off, u.src, u.bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "copy to device");
+    }
+    gtls::BatchArgsHost a{offsets, period_offsets, n_curves, (double*)(b + o_t), (double*)(b + o_y),
+                          (double*)(b + o_dy), (double*)(b + o_p), (double*)(b + o_d), n_durations,
+                          (double*)(b + o_tm), n_tmpl, prm, (double*)(b + o_chi2), (int32_t*)(b + o_bd),
+                          (int32_t*)(b + o_bs), (double*)(b + o_dep), (double*)(b + o_t0), (double*)(b + o_sr),
+                          (double*)(b + o_raw), (double*)(b + o_sde), (gtls_summary*)(b + o_sum)};
+    e = gtls::run_search_batch(ctx, a);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batched search");
+    struct Down { void* dst; size_t off; size_t bytes; } downs[] = {
+        {chi2, o_chi2, 8 * np}, {best_dur, o_bd, 4 * np}, {best_start, o_bs, 4 * np}, {depth, o_dep, 8 * np},
+        {t0, o_t0, 8 * np}, {sde, o_sde, 8 * np}, {summaries, o_sum, sizeof(gtls_summary) * nc}};
+    for (const Down& d : downs) {
+        if (!d.dst) continue;
+        e = hipMemcpyAsync(d.dst, b + d.off, d.bytes, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
     return GTLS_OK;
 }
 

@@ -54,6 +54,38 @@ struct DeviceBuffer {
     size_t bytes = 0;
 };
 
+// Batched survey: host CSR offsets, device data and outputs.
+struct BatchArgsHost {
+    const int64_t* offsets;        // host [nc + 1]
+    const int64_t* poffsets;       // host [nc + 1]
+    int32_t nc;
+    const double* t;               // device
+    const double* y;
+    const double* dy;
+    const double* periods;
+    const double* durations;
+    int32_t nd;
+    const double* tmpl;
+    int32_t nt;
+    gtls_params prm;
+    double* chi2;                  // device outputs (CSR over periods)
+    int32_t* best_dur;
+    int32_t* best_start;
+    double* depth;
+    double* t0;
+    double* sr;
+    double* sde_raw;
+    double* sde;
+    gtls_summary* summaries;       // device [nc]
+};
+
+// Cached executable graph of the batched pipeline and autotuned grid sizes.
+struct BatchCache {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+    std::vector<std::pair<std::vector<uint64_t>, int>> tuned;   // shape key -> workgroups per CU
+};
+
 }  // namespace gtls
 
 struct gtls_ctx {
@@ -67,6 +99,10 @@ struct gtls_ctx {
     gtls::DeviceBuffer io;       // device copies for host-pointer calls
     gtls::DeviceBuffer sde_tmp;  // SDE scratch
     gtls::DeviceBuffer table;    // template rows per point count D and per-D sums
+    gtls::DeviceBuffer bcurve;   // batched: per-point arrays, per-curve scalars, queue
+    gtls::DeviceBuffer bscratch; // batched: per-workgroup sort/padding scratch
+    gtls::BatchCache bcache;
+    int num_cus = 0;
     // per-stage timing (gtls_profile_enable / gtls_profile_read)
     bool profiling = false;
     double prof_ms[8] = {0};
@@ -88,6 +124,7 @@ hipError_t run_fold_sort(gtls_ctx* ctx, const double* t_dev, int64_t n, const do
 hipError_t run_sde(gtls_ctx* ctx, const double* chi2_dev, int32_t n, int32_t window, double* sr_dev,
                    double* raw_dev, double* sde_dev, gtls_summary* summary_dev);
 hipError_t ensure(gtls_ctx* ctx, DeviceBuffer& b, size_t bytes);
+hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& a);
 hipError_t profile_collect(gtls_ctx* ctx);
 
 enum Stage { kStagePrep = 0, kStageSort = 1, kStageSlide = 2, kStageReduce = 3, kStageSde = 4 };

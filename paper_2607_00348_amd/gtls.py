@@ -23,7 +23,8 @@ GTLS_DEPTH_WLS, GTLS_DEPTH_MEAN = 0, 1
 
 EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_default", "gtls_sync",
             "gtls_profile_enable", "gtls_profile_read",
-            "tls_search", "tls_search_dev", "tls_fold_sort", "tls_sde", "gtls_period_grid_ofir",
+            "tls_search", "tls_search_dev", "tls_search_batch", "tls_search_batch_dev", "tls_fold_sort",
+            "tls_sde", "gtls_period_grid_ofir",
             "gtls_duration_grid", "gtls_template_quadratic"]
 
 
@@ -93,6 +94,15 @@ def lib():
         L.tls_search_dev.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, ctypes.c_int32,
                                      vp, ctypes.c_int32, ctypes.POINTER(gtls_params), vp, vp, vp, vp, vp, vp,
                                      vp, vp, vp]
+        lp = ctypes.POINTER(ctypes.c_int64)
+        L.tls_search_batch.restype = ctypes.c_int
+        L.tls_search_batch.argtypes = [vp, lp, _dp, _dp, _dp, ctypes.c_int32, lp, _dp, _dp, ctypes.c_int32, _dp,
+                                       ctypes.c_int32, ctypes.POINTER(gtls_params), _dp, _ip, _ip, _dp, _dp, _dp,
+                                       ctypes.POINTER(gtls_summary)]
+        L.tls_search_batch_dev.restype = ctypes.c_int
+        L.tls_search_batch_dev.argtypes = [vp, lp, vp, vp, vp, ctypes.c_int32, lp, vp, vp, ctypes.c_int32, vp,
+                                           ctypes.c_int32, ctypes.POINTER(gtls_params), vp, vp, vp, vp, vp, vp, vp,
+                                           vp, vp]
         L.tls_fold_sort.restype = ctypes.c_int
         L.tls_fold_sort.argtypes = [vp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _ip]
         L.tls_sde.restype = ctypes.c_int
@@ -220,6 +230,60 @@ def tls_search_dev(ctx: Context, time, flux, dy, n: int, period_grid, n_periods:
                                 v(duration_grid), int(n_durations), v(tmpl), int(n_tmpl), ctypes.byref(prm),
                                 v(chi2), v(best_dur), v(best_start), v(depth), v(t0), v(sr), v(sde_raw), v(sde),
                                 v(summary)), ctx.ptr)
+
+
+@dataclass
+class BatchResult:
+    chi2: np.ndarray          # CSR over all curves' periods
+    best_dur: np.ndarray
+    best_start: np.ndarray
+    depth: np.ndarray
+    t0: np.ndarray
+    sde: np.ndarray
+    summaries: np.ndarray     # structured: chi2_null, sde_max, n_evals, n_macs, best_period
+
+
+SUMMARY_DTYPE = np.dtype([("chi2_null", "<f8"), ("sde_max", "<f8"), ("n_evals", "<i8"), ("n_macs", "<i8"),
+                          ("best_period", "<i4"), ("pad_", "<i4")])
+
+
+def tls_search_batch(ctx: Context, offsets, time, flux, dy, period_offsets, periods, duration_grid, tmpl,
+                     params: gtls_params | None = None) -> BatchResult:
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    poff = np.ascontiguousarray(period_offsets, dtype=np.int64)
+    t, y, e = _f64(time), _f64(flux), _f64(dy)
+    per, dur, tm = _f64(periods), _f64(duration_grid), _f64(tmpl)
+    nc = len(off) - 1
+    npd = int(poff[-1])
+    out = {k: np.empty(npd) for k in ("chi2", "depth", "t0", "sde")}
+    bd = np.empty(npd, dtype=np.int32)
+    bs = np.empty(npd, dtype=np.int32)
+    summ = np.zeros(nc, dtype=SUMMARY_DTYPE)
+    prm = params if params is not None else gtls_params_default()
+    lp = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().tls_search_batch(ctx.ptr, off.ctypes.data_as(lp), _p(t), _p(y), _p(e), nc,
+                                  poff.ctypes.data_as(lp), _p(per), _p(dur), len(dur), _p(tm), len(tm),
+                                  ctypes.byref(prm), _p(out["chi2"]), bd.ctypes.data_as(_ip),
+                                  bs.ctypes.data_as(_ip), _p(out["depth"]), _p(out["t0"]), _p(out["sde"]),
+                                  summ.ctypes.data_as(ctypes.POINTER(gtls_summary))), ctx.ptr)
+    return BatchResult(best_dur=bd, best_start=bs, summaries=summ, **out)
+
+
+def tls_search_batch_dev(ctx: Context, offsets, time, flux, dy, period_offsets, periods, n_durations_ptr,
+                         n_durations: int, tmpl, n_tmpl: int, params: gtls_params | None, chi2, best_dur,
+                         best_start, depth, t0, sr, sde_raw, sde, summaries):
+    """offsets / period_offsets are host arrays; all other arrays are device
+    addresses (ints).  Enqueues and returns."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    poff = np.ascontiguousarray(period_offsets, dtype=np.int64)
+    prm = params if params is not None else gtls_params_default()
+    v = ctypes.c_void_p
+    lp = ctypes.POINTER(ctypes.c_int64)
+    _check(lib().tls_search_batch_dev(ctx.ptr, off.ctypes.data_as(lp), v(time), v(flux), v(dy), len(off) - 1,
+                                      poff.ctypes.data_as(lp), v(periods), v(n_durations_ptr), int(n_durations),
+                                      v(tmpl), int(n_tmpl), ctypes.byref(prm), v(chi2), v(best_dur),
+                                      v(best_start), v(depth), v(t0), v(sr), v(sde_raw), v(sde), v(summaries)),
+           ctx.ptr)
 
 
 def tls_fold_sort(ctx: Context, time, periods) -> np.ndarray:

@@ -219,3 +219,34 @@ def random_chi2_series(seed: int, n: int) -> np.ndarray:
     k = int(g.integers(0, n))
     base[k] -= 40.0
     return base
+
+
+def survey_curve(index: int, n_curves: int = 4096, seed: int = 2, n_min: int = 4000,
+                 n_max: int = 147000) -> dict:
+    """Curve `index` of the batched Kepler-like survey: length uniform in
+    [n_min, n_max] cadences of 29.4 min, white noise with sigma log-uniform in
+    [50, 2000] ppm (dy = sigma), and for the first 10 % of a seeded
+    permutation of the curves an injected transit: P log-uniform in
+    [1, 200] d (at most half the baseline), p ~ U(0.01, 0.1), u1 ~ U(0.2, 0.6),
+    u2 ~ U(0.1, 0.4), b = 0, T14 of a circular orbit around a Sun-like star,
+    T0 ~ U(0, P)."""
+    perm = rng(seed).permutation(n_curves)
+    injected = set(perm[: max(1, n_curves // 10)].tolist())
+    g = rng(seed * 1_000_003 + index + 1)
+    n = int(g.integers(n_min, n_max + 1))
+    t = np.arange(n, dtype=np.float64) * KEPLER_CADENCE_DAYS
+    sigma = float(math.exp(g.uniform(math.log(50e-6), math.log(2000e-6))))
+    y = np.ones(n)
+    tr = None
+    if index in injected:
+        span = n * KEPLER_CADENCE_DAYS
+        period = float(math.exp(g.uniform(math.log(1.0), math.log(min(200.0, span / 2)))))
+        p = float(g.uniform(0.01, 0.1))
+        u1, u2 = float(g.uniform(0.2, 0.6)), float(g.uniform(0.1, 0.4))
+        norm = 1.0 - u1 / 3.0 - u2 / 6.0
+        depth = p * p * (1.0 - 0.0) / norm                           # central transit, limb-darkened centre
+        t14 = grazing_t14(period, 0.0, p)
+        tr = dict(period=period, t0=float(g.uniform(0.0, period)), t14=t14, depth=depth, u1=u1, u2=u2, b=0.0)
+        y = y - transit_deficit(t, **tr)
+    y = y + sigma * g.standard_normal(n)
+    return _curve(t, _to_fp32_flux(y), np.full(n, sigma), transit=tr, sigma=sigma, name=f"survey_{index}")
