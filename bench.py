@@ -70,22 +70,112 @@ def cpu_baseline(c, periods, durs, tm, prm, n_sample: int, seed: int = 0):
                       f"and dt0; {r.n_evals} windows in {el:.1f} s"}
 
 
+def survey_bench(args):
+    """Batched survey: a seeded sample of the 4096-curve Kepler-like survey
+    (lengths 4k-147k cadences, sigma 50-2000 ppm, 10 % injected), each curve
+    on its own default grid (Roche limit to half the baseline, oversampling
+    3), 20 shared durations, searched by one persistent launch per batch."""
+    import torch
+
+    from paper_2607_00348_amd import gtls, synth
+    g = np.random.Generator(np.random.PCG64(17))
+    idx = np.sort(g.choice(4096, size=args.curves, replace=False))
+    curves = [synth.survey_curve(int(i)) for i in idx]
+    grids = []
+    for c in curves:
+        span = c["t"][-1] - c["t"][0]
+        grids.append(gtls.gtls_period_grid_ofir(span, 3.0))
+    durs = gtls.gtls_duration_grid(float(min(gr[0] for gr in grids)), 1500.0, 20)
+    tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    prm = gtls.gtls_params_default(dt0=args.dt0,
+                                   precision=(gtls.GTLS_FP32C if args.precision == "fp32c" else gtls.GTLS_FP64))
+    off = np.cumsum([0] + [len(c["t"]) for c in curves])
+    poff = np.cumsum([0] + [len(gr) for gr in grids])
+    dev = torch.device("cuda:0")
+    f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    cat = lambda k: np.concatenate([c[k] for c in curves])
+    t_d, y_d, dy_d = f64(cat("t")), f64(cat("y")), f64(cat("dy"))
+    p_d, d_d, tm_d = f64(np.concatenate(grids)), f64(durs), f64(tm)
+    npd = int(poff[-1])
+    outs = {k: torch.empty(npd, dtype=torch.float64, device=dev) for k in ("chi2", "depth", "t0", "sr", "raw", "sde")}
+    bd = torch.empty(npd, dtype=torch.int32, device=dev)
+    bs = torch.empty(npd, dtype=torch.int32, device=dev)
+    summ = torch.zeros(len(curves) * 5, dtype=torch.int64, device=dev)
+    ctx = gtls.Context(0, torch.cuda.current_stream().cuda_stream)
+
+    def step():
+        gtls.tls_search_batch_dev(ctx, off, t_d.data_ptr(), y_d.data_ptr(), dy_d.data_ptr(), poff, p_d.data_ptr(),
+                                  d_d.data_ptr(), len(durs), tm_d.data_ptr(), len(tm), prm, outs["chi2"].data_ptr(),
+                                  bd.data_ptr(), bs.data_ptr(), outs["depth"].data_ptr(), outs["t0"].data_ptr(),
+                                  outs["sr"].data_ptr(), outs["raw"].data_ptr(), outs["sde"].data_ptr(),
+                                  summ.data_ptr())
+
+    print(f"[bench] survey sample: {len(curves)} curves, {off[-1]} points, {npd} (curve, period) items",
+          file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    sm = summ.cpu().numpy().reshape(len(curves), 5)
+    n_evals = int(sm[:, 2].sum())
+    line = {"metric": "light curves/hr (batched survey)", "value": len(curves) / el * 3600.0,
+            "unit": "light curves/hr", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
+            "config": {"workload": "kepler_survey_sample", "curves": len(curves), "points": int(off[-1]),
+                       "items": npd, "durations": len(durs), "dt0": args.dt0, "precision": args.precision},
+            "evals_per_s": n_evals / el}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def copy_probe(nbytes: int):
+    """A plain device-to-device copy of a known size (calibrates the HBM
+    byte counters of a profiler against an exactly known traffic)."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="kepler_3000d", choices=["kepler_3000d", "kepler_90d", "tess_13sector"])
+    ap.add_argument("--workload", default="kepler_3000d",
+                    choices=["kepler_3000d", "kepler_90d", "tess_13sector", "survey"])
+    ap.add_argument("--curves", type=int, default=32, help="survey sample size (--workload survey)")
     ap.add_argument("--dt0", type=float, default=0.1)
     ap.add_argument("--depth-mode", choices=["wls", "mean"], default="wls")
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="periods the oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the search shards periods across GPUs by design, "
               "but this build measures the single-GPU kernel path; use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "survey":
+        survey_bench(args)
+        return
 
     import torch
 

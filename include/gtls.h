@@ -220,6 +220,55 @@ gtls_status tls_fold_sort(gtls_ctx *ctx, const double *time, int64_t n,
 gtls_status tls_sde(gtls_ctx *ctx, const double *chi2, int32_t n, int32_t window,
                     double *sr, double *sde_raw, double *sde, int32_t *best);
 
+/* ---------------- learned period proposal ---------------- */
+/* A small 1D CNN ranks log-period bins so the full search can run on the
+ * periods of the top-ranked bins only (the full grid stays the fallback).
+ * Input: a 4096-bin view of the light curve (per-bin median flux, minus 1,
+ * over 1.4826 x the curve's median absolute deviation; empty bins 0).
+ * Network: 5 x [conv1d, 32 channels, kernel 7, padding 3, GELU (erf)],
+ * mean over positions, linear 32 -> 512, softmax cross-entropy.  BF16
+ * operands with FP32 accumulation on the matrix cores; FP32 master weights
+ * and Adam (beta 0.9/0.999, eps 1e-8).  Parameters are one flat FP32 vector:
+ * W0, b0, ..., W4, b4 (W_l shaped 32 x C_in x 7), Wf (512 x 32), bf (512). */
+#define GTLS_CNN_VIEW 4096
+#define GTLS_CNN_BINS 512
+typedef struct gtls_cnn gtls_cnn;
+
+/* Number of parameters (45,952). */
+int64_t gtls_cnn_num_params(void);
+
+/* Create a network on ctx's device from host FP32 initial parameters
+ * (gtls_cnn_num_params values; the caller chooses the random init). */
+gtls_status gtls_cnn_create(gtls_ctx *ctx, const float *init_params, gtls_cnn **net);
+
+/* Release a network.  NULL is a no-op. */
+void gtls_cnn_destroy(gtls_cnn *net);
+
+/* Views of n_curves curves in CSR layout (offsets [n_curves + 1], host):
+ * time non-decreasing within each curve, at least one point each.  Writes
+ * views [n_curves][4096] (host).  Synchronous. */
+gtls_status gtls_cnn_view(gtls_ctx *ctx, const int64_t *offsets, const double *time,
+                          const double *flux, int32_t n_curves, float *views);
+
+/* logits [B][512] for views [B][4096] (host arrays).  Synchronous. */
+gtls_status gtls_cnn_forward(gtls_cnn *net, const float *views, int32_t B, float *logits);
+
+/* Mean cross-entropy of the batch against labels [B] (bins 0..511) and its
+ * gradient (flat like the parameters; grads may be NULL).  No update. */
+gtls_status gtls_cnn_gradients(gtls_cnn *net, const float *views, const int32_t *labels,
+                               int32_t B, float *loss, float *grads);
+
+/* One Adam step at learning rate lr on the batch; *loss is its mean loss. */
+gtls_status gtls_cnn_train_step(gtls_cnn *net, const float *views, const int32_t *labels,
+                                int32_t B, float lr, float *loss);
+
+/* Copy the FP32 master parameters to host. */
+gtls_status gtls_cnn_get_params(gtls_cnn *net, float *params);
+
+/* The k highest-scoring bins per view, best first (ties: lower bin):
+ * bins [B][k], 1 <= k <= 512. */
+gtls_status gtls_cnn_topk(gtls_cnn *net, const float *views, int32_t B, int32_t k, int32_t *bins);
+
 /* ---------------- host-side helpers (no device needed) ---------------- */
 
 /* Cubic frequency grid of Sect. 2.2.1 as ascending periods in days.

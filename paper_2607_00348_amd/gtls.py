@@ -25,7 +25,10 @@ EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_defau
             "gtls_profile_enable", "gtls_profile_read",
             "tls_search", "tls_search_dev", "tls_search_batch", "tls_search_batch_dev", "tls_fold_sort",
             "tls_sde", "gtls_period_grid_ofir",
-            "gtls_duration_grid", "gtls_template_quadratic"]
+            "gtls_duration_grid", "gtls_template_quadratic", "gtls_cnn_num_params", "gtls_cnn_create",
+            "gtls_cnn_destroy", "gtls_cnn_view", "gtls_cnn_forward", "gtls_cnn_gradients", "gtls_cnn_train_step",
+            "gtls_cnn_get_params", "gtls_cnn_topk"]
+CNN_VIEW, CNN_BINS = 4096, 512
 
 
 class gtls_params(ctypes.Structure):
@@ -112,6 +115,25 @@ def lib():
         L.gtls_duration_grid.restype = ctypes.c_int
         L.gtls_duration_grid.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, _dp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.gtls_cnn_num_params.restype = ctypes.c_int64
+        L.gtls_cnn_num_params.argtypes = []
+        L.gtls_cnn_create.restype = ctypes.c_int
+        L.gtls_cnn_create.argtypes = [vp, fp, ctypes.POINTER(vp)]
+        L.gtls_cnn_destroy.restype = None
+        L.gtls_cnn_destroy.argtypes = [vp]
+        L.gtls_cnn_view.restype = ctypes.c_int
+        L.gtls_cnn_view.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), _dp, _dp, ctypes.c_int32, fp]
+        L.gtls_cnn_forward.restype = ctypes.c_int
+        L.gtls_cnn_forward.argtypes = [vp, fp, ctypes.c_int32, fp]
+        L.gtls_cnn_gradients.restype = ctypes.c_int
+        L.gtls_cnn_gradients.argtypes = [vp, fp, _ip, ctypes.c_int32, fp, fp]
+        L.gtls_cnn_train_step.restype = ctypes.c_int
+        L.gtls_cnn_train_step.argtypes = [vp, fp, _ip, ctypes.c_int32, ctypes.c_float, fp]
+        L.gtls_cnn_get_params.restype = ctypes.c_int
+        L.gtls_cnn_get_params.argtypes = [vp, fp]
+        L.gtls_cnn_topk.restype = ctypes.c_int
+        L.gtls_cnn_topk.argtypes = [vp, fp, ctypes.c_int32, ctypes.c_int32, _ip]
         L.gtls_template_quadratic.restype = ctypes.c_int
         L.gtls_template_quadratic.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int32, _dp]
         _lib = L
@@ -324,4 +346,100 @@ def gtls_template_quadratic(u1: float = 0.4, u2: float = 0.25, p: float = 0.01, 
                             m: int = 1024) -> np.ndarray:
     out = np.empty(int(m))
     _check(lib().gtls_template_quadratic(float(u1), float(u2), float(p), float(b), int(m), _p(out)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Learned period proposal
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def gtls_cnn_num_params() -> int:
+    return int(lib().gtls_cnn_num_params())
+
+
+class Cnn:
+    """gtls_cnn handle: a period-proposal network living on ctx's device."""
+
+    def __init__(self, ctx: Context, init_params):
+        self.ctx = ctx
+        self.ptr = ctypes.c_void_p()
+        p = np.ascontiguousarray(init_params, dtype=np.float32)
+        if len(p) != gtls_cnn_num_params():
+            raise ValueError("wrong parameter count")
+        _check(lib().gtls_cnn_create(ctx.ptr, _fp(p), ctypes.byref(self.ptr)), ctx.ptr)
+
+    def close(self):
+        if self.ptr:
+            lib().gtls_cnn_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gtls_cnn_create(ctx: Context, init_params) -> Cnn:
+    return Cnn(ctx, init_params)
+
+
+def gtls_cnn_destroy(net: Cnn):
+    net.close()
+
+
+def gtls_cnn_view(ctx: Context, offsets, time, flux) -> np.ndarray:
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    t, y = _f64(time), _f64(flux)
+    nc = len(off) - 1
+    out = np.empty((nc, CNN_VIEW), dtype=np.float32)
+    _check(lib().gtls_cnn_view(ctx.ptr, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p(t), _p(y), nc,
+                               _fp(out)), ctx.ptr)
+    return out
+
+
+def _views(v):
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    return v.reshape(-1, CNN_VIEW)
+
+
+def gtls_cnn_forward(net: Cnn, views) -> np.ndarray:
+    v = _views(views)
+    out = np.empty((len(v), CNN_BINS), dtype=np.float32)
+    _check(lib().gtls_cnn_forward(net.ptr, _fp(v), len(v), _fp(out)), net.ctx.ptr)
+    return out
+
+
+def gtls_cnn_gradients(net: Cnn, views, labels):
+    v = _views(views)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    g = np.empty(gtls_cnn_num_params(), dtype=np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(lib().gtls_cnn_gradients(net.ptr, _fp(v), lab.ctypes.data_as(_ip), len(v), ctypes.byref(loss), _fp(g)),
+           net.ctx.ptr)
+    return float(loss.value), g
+
+
+def gtls_cnn_train_step(net: Cnn, views, labels, lr: float = 1e-3) -> float:
+    v = _views(views)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    loss = ctypes.c_float(0.0)
+    _check(lib().gtls_cnn_train_step(net.ptr, _fp(v), lab.ctypes.data_as(_ip), len(v), float(lr),
+                                     ctypes.byref(loss)), net.ctx.ptr)
+    return float(loss.value)
+
+
+def gtls_cnn_get_params(net: Cnn) -> np.ndarray:
+    out = np.empty(gtls_cnn_num_params(), dtype=np.float32)
+    _check(lib().gtls_cnn_get_params(net.ptr, _fp(out)), net.ctx.ptr)
+    return out
+
+
+def gtls_cnn_topk(net: Cnn, views, k: int) -> np.ndarray:
+    v = _views(views)
+    out = np.empty((len(v), int(k)), dtype=np.int32)
+    _check(lib().gtls_cnn_topk(net.ptr, _fp(v), len(v), int(k), out.ctypes.data_as(_ip)), net.ctx.ptr)
     return out

@@ -1,0 +1,178 @@
+"""Learned period proposal: data, training and evaluation driver.
+
+The network (a small 1D CNN, see include/gtls.h) ranks 512 log-period bins
+of a curve from its 4096-bin view; the full TLS search then runs only on the
+grid periods inside the top-k bins.  Labels are the best period (largest SDE)
+of the full-grid search, computed with the batched GPU search (which is
+bit-exact against the CPU oracle).  Everything here calls the C ABI through
+``gtls``; the oracle is not used.
+
+Run: ``python -m paper_2607_00348_amd.learned --train 8192 --test 1024``
+writes a JSON summary (recall@k of the network and of the prior-only
+ranking, and the speed-up of the pruned search over the full grid).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import gtls, synth
+
+PMIN, PMAX = 0.5, 45.0          # 90-day Kepler-like curves: grid 0.5 .. 45 d
+N_BINS = 512
+N_CAD = 4409
+
+
+def bin_edges() -> np.ndarray:
+    return PMIN * (PMAX / PMIN) ** (np.arange(N_BINS + 1) / N_BINS)
+
+
+def period_bin(p: np.ndarray) -> np.ndarray:
+    return np.clip(np.floor(np.log(np.asarray(p) / PMIN) / math.log(PMAX / PMIN) * N_BINS), 0, N_BINS - 1).astype(
+        np.int32)
+
+
+def training_curve(index: int, seed: int) -> dict:
+    """90-day, 29.4-min cadence curve; sigma log-uniform in [100, 400] ppm;
+    70 % carry a transit with P log-uniform in [0.6, 40] d, depth 2-8 sigma
+    per point, T14 of a circular orbit around a Sun-like star."""
+    g = synth.rng(seed * 1_000_003 + index)
+    t = np.arange(N_CAD, dtype=np.float64) * synth.KEPLER_CADENCE_DAYS
+    sigma = float(math.exp(g.uniform(math.log(100e-6), math.log(400e-6))))
+    y = np.ones(N_CAD)
+    tr = None
+    if g.uniform() < 0.7:
+        period = float(math.exp(g.uniform(math.log(0.6), math.log(40.0))))
+        depth = float(g.uniform(2.0, 8.0) * sigma)
+        p = math.sqrt(depth)
+        tr = dict(period=period, t0=float(g.uniform(0, period)), t14=synth.grazing_t14(period, 0.0, p),
+                  depth=depth, u1=float(g.uniform(0.2, 0.6)), u2=float(g.uniform(0.1, 0.4)), b=0.0)
+        y = y - synth.transit_deficit(t, **tr)
+    y = y + sigma * g.standard_normal(N_CAD)
+    return {"t": t, "y": y.astype(np.float32).astype(np.float64), "dy": np.full(N_CAD, sigma), "meta": tr}
+
+
+def search_inputs():
+    span = (N_CAD - 1) * synth.KEPLER_CADENCE_DAYS
+    grid = gtls.gtls_period_grid_ofir(span, 3.0, pmin_days=PMIN, pmax_days=PMAX)
+    durs = gtls.gtls_duration_grid(PMIN, PMAX, 12)
+    tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    return grid, durs, tm
+
+
+def batched_search(ctx, curves, grids, durs, tm, params=None, chunk=512):
+    """Full search of many curves (each its own grid) through the batched
+    path, in chunks; returns per-curve (best period, SDE max, chi2 array)."""
+    best, sde, chi2 = [], [], []
+    for c0 in range(0, len(curves), chunk):
+        cs = curves[c0:c0 + chunk]
+        gs = grids[c0:c0 + chunk]
+        off = np.cumsum([0] + [len(c["t"]) for c in cs])
+        poff = np.cumsum([0] + [len(g) for g in gs])
+        r = gtls.tls_search_batch(ctx, off, np.concatenate([c["t"] for c in cs]),
+                                  np.concatenate([c["y"] for c in cs]), np.concatenate([c["dy"] for c in cs]),
+                                  poff, np.concatenate(gs), durs, tm, params)
+        for k in range(len(cs)):
+            best.append(gs[k][r.summaries[k]["best_period"]])
+            sde.append(float(r.summaries[k]["sde_max"]))
+            chi2.append(r.chi2[poff[k]:poff[k + 1]])
+    return np.array(best), np.array(sde), chi2
+
+
+def views_of(ctx, curves) -> np.ndarray:
+    off = np.cumsum([0] + [len(c["t"]) for c in curves])
+    return gtls.gtls_cnn_view(ctx, off, np.concatenate([c["t"] for c in curves]),
+                              np.concatenate([c["y"] for c in curves]))
+
+
+def train(ctx, views, labels, steps: int, batch: int = 64, lr: float = 1e-3, seed: int = 0, log=None):
+    net = gtls.Cnn(ctx, synth.cnn_init(seed).astype(np.float32))
+    g = synth.rng(seed + 1)
+    losses = []
+    for s in range(steps):
+        idx = g.integers(0, len(views), batch)
+        lr_s = lr * min(1.0, (s + 1) / 100) * (0.5 * (1 + math.cos(math.pi * s / steps)))
+        losses.append(gtls.gtls_cnn_train_step(net, views[idx], labels[idx], lr=lr_s))
+        if log and (s % max(1, steps // 10) == 0 or s == steps - 1):
+            log(f"step {s}: loss {np.mean(losses[-50:]):.4f}")
+    return net, losses
+
+
+def recall_at_k(ranked_bins: np.ndarray, labels: np.ndarray) -> float:
+    return float(np.mean([labels[i] in set(ranked_bins[i].tolist()) for i in range(len(labels))]))
+
+
+def run(n_train: int, n_test: int, steps: int, k: int = 32, seed: int = 0, log=print) -> dict:
+    ctx = gtls.Context(0)
+    grid, durs, tm = search_inputs()
+    log(f"grid {len(grid)} periods, {len(durs)} durations")
+    t0 = time.perf_counter()
+    train_c = [training_curve(i, seed) for i in range(n_train)]
+    test_c = [training_curve(10_000_000 + i, seed) for i in range(n_test)]
+    log(f"curves generated in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    tr_best, tr_sde, _ = batched_search(ctx, train_c, [grid] * n_train, durs, tm)
+    log(f"training labels (full-grid searches) in {time.perf_counter() - t0:.1f} s")
+    tr_lab = period_bin(tr_best)
+    v_tr = views_of(ctx, train_c)
+    t0 = time.perf_counter()
+    net, losses = train(ctx, v_tr, tr_lab, steps, seed=seed, log=log)
+    t_train = time.perf_counter() - t0
+    log(f"trained {steps} steps in {t_train:.1f} s")
+
+    # held-out: full search (timed), then view + network + pruned search (timed)
+    gtls.gtls_sync(ctx)
+    t0 = time.perf_counter()
+    te_best, te_sde, _ = batched_search(ctx, test_c, [grid] * n_test, durs, tm)
+    t_full = time.perf_counter() - t0
+    te_lab = period_bin(te_best)
+    t0 = time.perf_counter()
+    v_te = views_of(ctx, test_c)
+    top = gtls.gtls_cnn_topk(net, v_te, k)
+    gbin = period_bin(grid)
+    sub = [grid[np.isin(gbin, top[i])] for i in range(n_test)]
+    sub = [s if len(s) else grid[:1] for s in sub]
+    pr_best, _, _ = batched_search(ctx, test_c, sub, durs, tm)
+    t_pruned = time.perf_counter() - t0
+    prior = np.argsort(-np.bincount(tr_lab, minlength=N_BINS), kind="stable")[:k]
+    strong = te_sde >= 7.0
+    out = {
+        "n_train": n_train, "n_test": n_test, "steps": steps, "k": k, "grid_periods": int(len(grid)),
+        "final_loss": float(np.mean(losses[-50:])), "train_seconds": t_train,
+        "recall_net": recall_at_k(top, te_lab),
+        "recall_net_sde7": recall_at_k(top[strong], te_lab[strong]) if strong.any() else None,
+        "recall_prior": recall_at_k(np.tile(prior, (n_test, 1)), te_lab),
+        "recall_prior_sde7": recall_at_k(np.tile(prior, (int(strong.sum()), 1)), te_lab[strong]) if strong.any() else None,
+        "frac_sde7": float(strong.mean()),
+        "pruned_grid_fraction": float(np.mean([len(s) for s in sub]) / len(grid)),
+        "pruned_recovers_best": float(np.mean(np.isclose(pr_best, te_best))),
+        "t_full_s": t_full, "t_pruned_s": t_pruned, "speedup": t_full / t_pruned,
+    }
+    net.close()
+    ctx.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--train", type=int, default=8192)
+    ap.add_argument("--test", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    res = run(a.train, a.test, a.steps, a.k, log=lambda m: print(f"[learned] {m}", file=sys.stderr, flush=True))
+    s = json.dumps(res)
+    print(s, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(s + "\n")
+
+
+if __name__ == "__main__":
+    main()

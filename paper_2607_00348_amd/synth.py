@@ -250,3 +250,20 @@ def survey_curve(index: int, n_curves: int = 4096, seed: int = 2, n_min: int = 4
         y = y - transit_deficit(t, **tr)
     y = y + sigma * g.standard_normal(n)
     return _curve(t, _to_fp32_flux(y), np.full(n, sigma), transit=tr, sigma=sigma, name=f"survey_{index}")
+
+
+def cnn_init(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters of the period-proposal network, flat in the
+    order W0, b0, ..., W4, b4, Wf, bf (W_l: 32 x C_in x 7, Wf: 512 x 32):
+    uniform in +-sqrt(6 / fan_in) for weights, zero biases.  The random draws
+    live here so the GPU network and the CPU reference start identically."""
+    g = rng(seed)
+    parts = []
+    for cin in (1, 32, 32, 32, 32):
+        a = math.sqrt(6.0 / (cin * 7))
+        parts.append(g.uniform(-a, a, 32 * cin * 7))
+        parts.append(np.zeros(32))
+    a = math.sqrt(6.0 / 32)
+    parts.append(g.uniform(-a, a, 512 * 32))
+    parts.append(np.zeros(512))
+    return np.concatenate(parts).astype(np.float64)

@@ -1,0 +1,115 @@
+"""Pins of the CPU reference of the period-proposal network (CPU only):
+finite differences, PyTorch-CPU autograd, torch.optim.Adam and a brute-force
+binned median all agree with it."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+from paper_2607_00348_amd import synth
+
+
+def _batch(seed, n=2):
+    g = synth.rng(seed)
+    x = g.normal(0.0, 1.0, (n, cnn.L))
+    labels = g.integers(0, cnn.NB, n)
+    return x, labels
+
+
+def test_param_count():
+    assert cnn.N_PARAMS == 32 * 7 + 32 + 4 * (32 * 32 * 7 + 32) + 512 * 32 + 512
+    assert len(synth.cnn_init(0)) == cnn.N_PARAMS
+
+
+def test_gradient_matches_finite_differences():
+    p = synth.cnn_init(3) * 1.0
+    p[cnn.N_PARAMS - 512:] = synth.rng(4).normal(0, 0.1, 512)     # non-zero output bias
+    x, lab = _batch(5)
+    _, gr = cnn.loss_and_grad(p, x, lab)
+    g = synth.rng(6)
+    # probe entries from every layer's weights and biases
+    offs, o = [], 0
+    for ws, bs in cnn.SHAPES:
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        offs += list(o + g.choice(nw, 3, replace=False)) + list(o + nw + g.choice(nb, 2, replace=False))
+        o += nw + nb
+    for i in offs:
+        h = 1e-5 * max(1.0, abs(p[i]))
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (cnn.loss_and_grad(pp, x, lab)[0] - cnn.loss_and_grad(pm, x, lab)[0]) / (2 * h)
+        assert abs(fd - gr[i]) <= 1e-6 * max(1e-3, abs(gr[i])) + 1e-9, (i, fd, gr[i])
+
+
+def _torch_net(p):
+    layers = cnn.unflatten(p)
+    ts = [(torch.tensor(w, dtype=torch.float64, requires_grad=True),
+           torch.tensor(b, dtype=torch.float64, requires_grad=True)) for w, b in layers]
+    return ts
+
+
+def test_matches_pytorch_autograd():
+    p = synth.cnn_init(7)
+    x, lab = _batch(8, n=3)
+    loss, gr = cnn.loss_and_grad(p, x, lab)
+    ts = _torch_net(p)
+    h = torch.tensor(x, dtype=torch.float64)[:, None, :]
+    for w, b in ts[:cnn.NL]:
+        h = torch.nn.functional.gelu(torch.nn.functional.conv1d(h, w, b, padding=3), approximate="none")
+    logits = torch.nn.functional.linear(h.mean(dim=2), ts[cnn.NL][0], ts[cnn.NL][1])
+    tl = torch.nn.functional.cross_entropy(logits, torch.tensor(lab))
+    tl.backward()
+    tg = np.concatenate([np.concatenate([w.grad.numpy().ravel(), b.grad.numpy().ravel()]) for w, b in ts])
+    assert abs(loss - tl.item()) < 1e-12 * abs(loss)
+    assert np.allclose(gr, tg, rtol=1e-9, atol=1e-14)
+    ol, _ = cnn.forward(p, x)
+    assert np.allclose(ol, logits.detach().numpy(), rtol=1e-12, atol=1e-13)
+
+
+def test_adam_matches_torch():
+    g = synth.rng(9)
+    p = g.normal(0, 1, 50)
+    grads = [g.normal(0, 1, 50) for _ in range(3)]
+    m = np.zeros(50)
+    v = np.zeros(50)
+    q = p.copy()
+    for s, gr in enumerate(grads, 1):
+        q, m, v = cnn.adam(q, gr, m, v, s, lr=1e-2)
+    tp = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    for gr in grads:
+        opt.zero_grad()
+        tp.grad = torch.tensor(gr, dtype=torch.float64)
+        opt.step()
+    assert np.allclose(q, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_view_brute_force():
+    c = synth.curve_random(12, n=9000, inject=True, sigma=300e-6)
+    v = cnn.view(c["t"], c["y"])
+    t, y = c["t"], c["y"]
+    span = t.max() - t.min()
+    med = sorted(y)[len(y) // 2] if len(y) % 2 else 0.5 * (sorted(y)[len(y) // 2 - 1] + sorted(y)[len(y) // 2])
+    dev = sorted(abs(y - med))
+    mad = dev[len(dev) // 2] if len(dev) % 2 else 0.5 * (dev[len(dev) // 2 - 1] + dev[len(dev) // 2])
+    bins = {}
+    for ti, yi in zip(t, y):
+        k = min(cnn.L - 1, int(math.floor((ti - t.min()) / span * cnn.L)))
+        bins.setdefault(k, []).append(yi)
+    ref = np.zeros(cnn.L)
+    for k, vals in bins.items():
+        s = sorted(vals)
+        m = s[len(s) // 2] if len(s) % 2 else 0.5 * (s[len(s) // 2 - 1] + s[len(s) // 2])
+        ref[k] = (m - 1.0) / (1.4826 * mad)
+    assert np.array_equal(v, ref)
+    assert np.all(cnn.view(t, np.ones_like(y)) == 0.0)
+
+
+def test_topk_and_bins():
+    lg = np.array([[0.1, 0.5, 0.5, -1.0, 2.0]])
+    assert cnn.topk_bins(lg, 3).tolist() == [[4, 1, 2]]
+    e = cnn.period_bins(0.5, 45.0, 512)
+    assert len(e) == 513 and abs(e[0] - 0.5) < 1e-15 and abs(e[-1] - 45.0) < 1e-12
