@@ -313,3 +313,33 @@ def sde(chi2, window: int = 91):
     best = ctypes.c_int32(0)
     lib().oracle_sde(_dp(chi2), n, int(window), _dp(sr), _dp(raw), _dp(out), ctypes.byref(best))
     return sr, raw, out, int(best.value)
+
+
+def tls_search_two_stage(t, y, dy, periods, durations, tmpl, dt0: float, n_refine: int, window: int = 91,
+                         **kw):
+    """Two-stage search (Sect. 2.5): the whole grid with T0 step dt0, then
+    every T0 offset on the n_refine periods of largest first-stage SDE (ties:
+    lower index); their results replace the first-stage ones and the SDE
+    periodogram is taken over the merged chi2.  Returns (SearchResult,
+    (sr, sde_raw, sde, best), refined mask)."""
+    periods = _f64(periods)
+    coarse = tls_search(t, y, dy, periods, durations, tmpl, dt0=dt0, **kw)
+    _, _, sde0, _ = sde(coarse.chi2, window)
+    order = sorted(range(len(periods)), key=lambda i: (-sde0[i], i))
+    pick = np.array(sorted(order[:max(0, min(n_refine, len(periods)))]), dtype=np.int64)
+    res = SearchResult(coarse.chi2.copy(), coarse.best_dur.copy(), coarse.best_start.copy(),
+                       coarse.depth.copy(), coarse.t0.copy(), coarse.dchi2.copy(), coarse.chi2_null,
+                       coarse.n_evals)
+    refined = np.zeros(len(periods), dtype=bool)
+    if len(pick):
+        fine = tls_search(t, y, dy, periods[pick], durations, tmpl, dt0=0.0, **kw)
+        for a, k in enumerate(pick):
+            res.chi2[k] = fine.chi2[a]
+            res.best_dur[k] = fine.best_dur[a]
+            res.best_start[k] = fine.best_start[a]
+            res.depth[k] = fine.depth[a]
+            res.t0[k] = fine.t0[a]
+            res.dchi2[k] = fine.dchi2[a]
+        res.n_evals += fine.n_evals
+        refined[pick] = True
+    return res, sde(res.chi2, window), refined

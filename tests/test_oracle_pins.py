@@ -409,3 +409,42 @@ def test_noiseless_injection_recovered(oracle):
     assert abs(r.depth[k] / tr["depth"] - 1) < 0.02
     dt = np.mod(r.t0[k] - tr["t0"] + 0.5 * periods[k], periods[k]) - 0.5 * periods[k]
     assert abs(dt) < 0.02
+
+
+# --------------------------------------------------------------------------
+# Two-stage search (Sect. 2.5)
+
+def _two_stage_case(oracle):
+    c = synth.curve_random(21, n=1500, inject=True)
+    span = c["t"].max() - c["t"].min()
+    periods = oracle.period_grid_ofir(span, 2.0, pmin_days=0.5, pmax_days=span / 2)[::3]
+    durs = oracle.duration_grid(periods[0], periods[-1], 8)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 128)
+    return c, periods, durs, tm
+
+
+def test_two_stage_limits(oracle):
+    """Refining nothing is the coarse search; refining everything is the
+    every-offset search; a partial refinement lowers chi2 only where it
+    refines (stride-1 windows include the strided ones)."""
+    c, periods, durs, tm = _two_stage_case(oracle)
+    coarse = oracle.tls_search(c["t"], c["y"], c["dy"], periods, durs, tm, dt0=0.2)
+    full = oracle.tls_search(c["t"], c["y"], c["dy"], periods, durs, tm, dt0=0.0)
+    r0, (_, _, sde0, best0), ref0 = oracle.tls_search_two_stage(c["t"], c["y"], c["dy"], periods, durs, tm,
+                                                               dt0=0.2, n_refine=0)
+    assert not ref0.any() and np.array_equal(r0.chi2, coarse.chi2) and r0.n_evals == coarse.n_evals
+    assert best0 == oracle.sde(coarse.chi2)[3]
+    rall, (_, _, sdea, besta), refa = oracle.tls_search_two_stage(c["t"], c["y"], c["dy"], periods, durs, tm,
+                                                                  dt0=0.2, n_refine=10 ** 6)
+    assert refa.all()
+    for k in ("chi2", "best_dur", "best_start", "depth"):
+        assert np.array_equal(getattr(rall, k), getattr(full, k)), k
+    assert besta == oracle.sde(full.chi2)[3]
+    rk, (_, _, sdek, bestk), refk = oracle.tls_search_two_stage(c["t"], c["y"], c["dy"], periods, durs, tm,
+                                                                dt0=0.2, n_refine=15)
+    assert refk.sum() == 15
+    assert np.all(rk.chi2[refk] <= coarse.chi2[refk]) and np.array_equal(rk.chi2[~refk], coarse.chi2[~refk])
+    assert np.array_equal(rk.chi2[refk], full.chi2[refk])
+    # the refined set is the 15 largest first-stage SDE values
+    _, _, sdec, _ = oracle.sde(coarse.chi2)
+    assert np.min(sdec[refk]) >= np.max(sdec[~refk])
