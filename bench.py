@@ -135,6 +135,26 @@ def survey_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def sort_bytes(n: int, periods, durs, prm) -> float:
+    """Algorithmic HBM bytes of the fold + sort + pad stage for one search:
+    per element-period 8 B of t, three radix passes over the packed 8-byte
+    (key, index) word (the first computes it: 8 B written; the others read
+    and write it: 32 B), and the padded residuals, 8 B (4 B in FP32C) per
+    position over n + D_max(P) positions, plus the weights when dy varies
+    (not in these workloads) and the 16 B (8 B) prefix sums in MEAN mode."""
+    p = np.asarray(periods)[:, None]
+    q = np.asarray(durs)[None, :] / p
+    ps = p * 86400.0
+    ok = (q <= prm.q_cap)
+    if prm.envelope:
+        ok &= (q ** 3 * ps ** 2 >= prm.k_min ** 3) & (q ** 3 * ps ** 2 <= prm.k_max ** 3)
+    d = np.clip(np.floor(n * q + 0.5), 1, n)
+    dmax = np.where(ok, d, 0).max(axis=1)
+    es = 4.0 if prm.precision == 1 else 8.0
+    per_pos = es + ((8.0 if prm.precision == 1 else 16.0) if prm.depth_mode == 1 else 0.0)
+    return float(np.sum(8.0 * n + 8.0 * n + 32.0 * n + per_pos * (n + dmax)))
+
+
 def copy_probe(nbytes: int):
     """A plain device-to-device copy of a known size (calibrates the HBM
     byte counters of a profiler against an exactly known traffic)."""
@@ -241,10 +261,7 @@ def main():
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "k_slide",
                 "per_launch_ms": stage_ms / launches}
     else:
-        n = len(c["t"])
-        dcap = min(n, math.floor(n * prm.q_cap + 0.5))
-        per_period = 8.0 * n + 4 * 16.0 * n + 8.0 * n + 8.0 * (n + dcap)
-        byts = per_period * npd
+        byts = sort_bytes(len(c["t"]), periods, durs, prm)
         achieved = byts / (stage_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_fold_sort",

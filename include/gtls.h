@@ -220,6 +220,22 @@ gtls_status tls_fold_sort(gtls_ctx *ctx, const double *time, int64_t n,
 gtls_status tls_sde(gtls_ctx *ctx, const double *chi2, int32_t n, int32_t window,
                     double *sr, double *sde_raw, double *sde, int32_t *best);
 
+/* Two-stage search (Sect. 2.5): the whole period grid with the T0 step
+ * params->dt0, then every T0 offset (dt0 = 0) on the n_refine periods with
+ * the largest first-stage SDE (ties: lower index).  At those periods the
+ * second-stage chi2, best duration, start, depth and T0 replace the first-
+ * stage ones, and sr, sde_raw, sde, best_period and sde_max are computed
+ * over the merged chi2.  n_evals / n_macs count both stages.  Arguments as
+ * in tls_search; n_refine >= 0 (0: the first stage alone; more than
+ * n_periods: every period); refined [n_periods] (may be NULL) receives 1 at
+ * the second-stage periods, else 0.  Synchronous. */
+gtls_status tls_search_refined(gtls_ctx *ctx, const double *time, const double *flux,
+                               const double *dy, int64_t n, const double *period_grid,
+                               int32_t n_periods, const double *duration_grid,
+                               int32_t n_durations, const double *tmpl, int32_t n_tmpl,
+                               const gtls_params *params, int32_t n_refine,
+                               gtls_result *out, uint8_t *refined);
+
 /* ---------------- learned period proposal ---------------- */
 /* A small 1D CNN ranks log-period bins so the full search can run on the
  * periods of the top-ranked bins only (the full grid stays the fallback).

@@ -2,9 +2,11 @@
 // wrappers around the device pipeline in kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "gtls_impl.hpp"
 
@@ -55,7 +57,7 @@ gtls_status check_host_data(gtls_ctx* ctx, const double* t, const double* y, con
         if (!std::isfinite(t[i]) || !std::isfinite(y[i])) return fail(ctx, GTLS_EINVAL, "non-finite time or flux");
         if (!(std::fabs(1.0 - y[i]) < 1024.0)) return fail(ctx, GTLS_EINVAL, "flux must satisfy |1 - y| < 1024");
         if (!(dy[i] > 0.0) || !std::isfinite(dy[i])) return fail(ctx, GTLS_EINVAL, "dy must be finite and > 0");
-        if (!(1.0 / (dy[i] * dy[i]) < INFINITY)) return fail(ctx, GTLS_EINVAL, "dy too small");
+        if (!(1.0 / (dy[i] * dy[i]) < 1e300)) return fail(ctx, GTLS_EINVAL, "dy too small");
     }
     for (int32_t k = 0; k < np; ++k) {
         if (!(per[k] > 0.0) || !std::isfinite(per[k])) return fail(ctx, GTLS_EINVAL, "periods must be finite and > 0");
@@ -435,6 +437,95 @@ gtls_status tls_sde(gtls_ctx* ctx, const double* chi2, int32_t n, int32_t window
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
     if (best) *best = sum.best_period;
+    return GTLS_OK;
+}
+
+gtls_status tls_search_refined(gtls_ctx* ctx, const double* time, const double* flux, const double* dy, int64_t n,
+                               const double* period_grid, int32_t n_periods, const double* duration_grid,
+                               int32_t n_durations, const double* tmpl, int32_t n_tmpl, const gtls_params* params,
+                               int32_t n_refine, gtls_result* out, uint8_t* refined) {
+    if (!ctx) return GTLS_EINVAL;
+    if (out) out->best_period = -1;
+    if (!out) return fail(ctx, GTLS_EINVAL, "out is null");
+    if (n_refine < 0) return fail(ctx, GTLS_EINVAL, "n_refine must be >= 0");
+    if (n_periods < 1) return fail(ctx, GTLS_EINVAL, "n_periods must be >= 1");
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    const size_t np = (size_t)n_periods;
+    // Stage 1: the whole grid with the coarse T0 step.
+    std::vector<double> chi2(np), depth(np), t0(np), sr(np), raw(np), sde(np);
+    std::vector<int32_t> bd(np), bs(np);
+    gtls_result c{};
+    c.chi2 = chi2.data();
+    c.best_dur = bd.data();
+    c.best_start = bs.data();
+    c.depth = depth.data();
+    c.t0 = t0.data();
+    c.sr = sr.data();
+    c.sde_raw = raw.data();
+    c.sde = sde.data();
+    gtls_status st = tls_search(ctx, time, flux, dy, n, period_grid, n_periods, duration_grid, n_durations, tmpl,
+                                n_tmpl, &prm, &c);
+    if (st != GTLS_OK) return st;
+    // Candidates: the n_refine largest coarse SDE values (ties: lower index),
+    // searched again in ascending period order.
+    const size_t k = std::min(np, (size_t)n_refine);
+    std::vector<int32_t> idx(np);
+    for (size_t i = 0; i < np; ++i) idx[i] = (int32_t)i;
+    std::partial_sort(idx.begin(), idx.begin() + (std::ptrdiff_t)k, idx.end(), [&](int32_t a, int32_t b) {
+        return sde[a] > sde[b] || (sde[a] == sde[b] && a < b);
+    });
+    idx.resize(k);
+    std::sort(idx.begin(), idx.end());
+    uint64_t evals = c.n_evals, macs = c.n_macs;
+    if (k > 0) {
+        // Stage 2: every T0 offset on the candidates; their results replace the coarse ones.
+        std::vector<double> per(k), fchi2(k), fdepth(k), ft0(k);
+        std::vector<int32_t> fbd(k), fbs(k);
+        for (size_t i = 0; i < k; ++i) per[i] = period_grid[idx[i]];
+        gtls_params fine = prm;
+        fine.dt0 = 0.0;
+        gtls_result f{};
+        f.chi2 = fchi2.data();
+        f.best_dur = fbd.data();
+        f.best_start = fbs.data();
+        f.depth = fdepth.data();
+        f.t0 = ft0.data();
+        st = tls_search(ctx, time, flux, dy, n, per.data(), (int32_t)k, duration_grid, n_durations, tmpl, n_tmpl,
+                        &fine, &f);
+        if (st != GTLS_OK) return st;
+        for (size_t i = 0; i < k; ++i) {
+            chi2[idx[i]] = fchi2[i];
+            bd[idx[i]] = fbd[i];
+            bs[idx[i]] = fbs[i];
+            depth[idx[i]] = fdepth[i];
+            t0[idx[i]] = ft0[i];
+        }
+        evals += f.n_evals;
+        macs += f.n_macs;
+        // The periodogram statistics over the merged chi2.
+        int32_t best = -1;
+        st = tls_sde(ctx, chi2.data(), n_periods, prm.median_window, sr.data(), raw.data(), sde.data(), &best);
+        if (st != GTLS_OK) return st;
+        c.best_period = best;
+        c.sde_max = sde[(size_t)best];
+    }
+    struct Out { void* dst; const void* src; size_t bytes; } outs[] = {
+        {out->chi2, chi2.data(), 8 * np}, {out->best_dur, bd.data(), 4 * np}, {out->best_start, bs.data(), 4 * np},
+        {out->depth, depth.data(), 8 * np}, {out->t0, t0.data(), 8 * np}, {out->sr, sr.data(), 8 * np},
+        {out->sde_raw, raw.data(), 8 * np}, {out->sde, sde.data(), 8 * np}};
+    for (const Out& o : outs)
+        if (o.dst) std::memcpy(o.dst, o.src, o.bytes);
+    if (refined) {
+        std::memset(refined, 0, np);
+        for (int32_t i : idx) refined[i] = 1;
+    }
+    out->chi2_null = c.chi2_null;
+    out->best_period = c.best_period;
+    out->sde_max = c.sde_max;
+    out->n_evals = evals;
+    out->n_macs = macs;
     return GTLS_OK;
 }
 

@@ -38,7 +38,6 @@ namespace {
 
 constexpr double kDay = 86400.0;
 constexpr double kTwo53 = 9007199254740992.0;
-constexpr double kTwo32 = 4294967296.0;
 
 // Layout of the per-curve scalar block (uint64 slots).
 enum MiscSlot { kChi2Null = 0, kTminOrd = 1, kWminBits = 2, kWmaxBits = 3, kEvals = 4, kMacs = 5, kMiscSlots = 8 };
@@ -236,39 +235,90 @@ __device__ __forceinline__ bool key_less(uint64_t a, uint64_t b, const double* _
 
 template <int NT>
 struct SortShared {
-    uint32_t hist[4][256];
+    uint32_t hist[3][256];
     uint32_t wcnt[NT / 64][256];
     uint32_t dbase[256];
     __int128 part[NT];
     int64_t dpad;
 };
 
+constexpr double kTwo24 = 16777216.0;
+constexpr uint32_t kKeyMax = (1u << 24) - 1;
+
+// 24-bit sort key floor(phi 2^24), monotone in phi; a phase that rounds up
+// to 1.0 (tiny negative t / P) takes the largest key, and the tie fix
+// places it by its FP64 value.
+__device__ __forceinline__ uint32_t phase_key(double ph) {
+    const double x = ph * kTwo24;
+    return x >= kTwo24 ? kKeyMax : (uint32_t)x;
+}
+
+// Where the sorted order goes: the padded residual / weight copies (npad
+// positions, position k holding sorted point k mod n), or nothing (rpad
+// null: permutation only).
+struct PadOut {
+    const double* r;
+    const double* w;
+    void* rpad;
+    void* wpad;
+    int64_t npad;
+    bool f32;
+};
+
+// Writes the residual (and weight) of input point idx at padded position
+// pos and, when pos + n is still inside the padding, at pos + n.
+__device__ __forceinline__ void pad_store(const PadOut& po, int64_t n, int64_t pos, uint32_t idx) {
+    const double rv = po.r[idx];
+    const double wv = po.wpad ? po.w[idx] : 0.0;
+    const bool twice = pos + n < po.npad;
+    if (po.f32) {
+        float* rp = (float*)po.rpad;
+        rp[pos] = (float)rv;
+        if (twice) rp[pos + n] = (float)rv;
+        if (po.wpad) {
+            float* wp = (float*)po.wpad;
+            wp[pos] = (float)wv;
+            if (twice) wp[pos + n] = (float)wv;
+        }
+    } else {
+        double* rp = (double*)po.rpad;
+        rp[pos] = rv;
+        if (twice) rp[pos + n] = rv;
+        if (po.wpad) {
+            double* wp = (double*)po.wpad;
+            wp[pos] = wv;
+            if (twice) wp[pos + n] = wv;
+        }
+    }
+}
+
 // Phase order of n points at `period`: A[k] = (phase key << 32 | index) of
-// the k-th point.  32-bit keys floor(phi 2^32), four stable 8-bit LSD passes
-// (A -> B -> A -> B -> A) ranked with wave ballots, then each run of equal
-// keys reordered by the full FP64 phase and the input index.
-template <int NT>
+// the k-th point, and (Sect. 2.3.2) the padded residuals in that order.
+// Three stable 8-bit LSD passes over 24-bit keys, ranked with wave ballots:
+// the first computes the keys from t (t -> A), the second moves A -> B, the
+// last B -> A and writes the padded copies.  Each run of equal keys is then
+// reordered by the full FP64 phase and the input index (and its padded
+// copies rewritten).  With PREFETCH every pass loads its next tile before
+// ranking the current one.
+template <int NT, bool PREFETCH>
 __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double period, uint64_t* A, uint64_t* B,
-                               SortShared<NT>& sh) {
+                               const PadOut& po, SortShared<NT>& sh) {
     constexpr int W = NT / 64;
     constexpr int TILE = NT * kSortItems;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    for (int k = tid; k < 4 * 256; k += NT) (&sh.hist[0][0])[k] = 0;
+    for (int k = tid; k < 3 * 256; k += NT) (&sh.hist[0][0])[k] = 0;
     for (int k = tid; k < W * 256; k += NT) (&sh.wcnt[0][0])[k] = 0;
     __syncthreads();
     for (int64_t i = tid; i < n; i += NT) {
-        const double ph = phase_of(t[i], period);
-        const uint32_t key = (uint32_t)(ph * kTwo32);
-        A[i] = ((uint64_t)key << 32) | (uint32_t)i;
+        const uint32_t key = phase_key(phase_of(t[i], period));
         atomicAdd(&sh.hist[0][key & 255u], 1u);
         atomicAdd(&sh.hist[1][(key >> 8) & 255u], 1u);
-        atomicAdd(&sh.hist[2][(key >> 16) & 255u], 1u);
-        atomicAdd(&sh.hist[3][key >> 24], 1u);
+        atomicAdd(&sh.hist[2][key >> 16], 1u);
     }
     __syncthreads();
-    if (tid < 4) {
+    if (tid < 3) {
         uint32_t run = 0;
         for (int d = 0; d < 256; ++d) {
             const uint32_t c = sh.hist[tid][d];
@@ -279,21 +329,39 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
     __syncthreads();
 
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t* src = A;
-    uint64_t* dst = B;
-    for (int pass = 0; pass < 4; ++pass) {
+    const bool gather = po.rpad != nullptr;
+    for (int pass = 0; pass < 3; ++pass) {
+        const uint64_t* src = (pass == 2) ? B : A;
+        uint64_t* dst = (pass == 1) ? B : A;
         if (tid < 256) sh.dbase[tid] = sh.hist[pass][tid];
         __syncthreads();
         const int shift = 32 + 8 * pass;
-        for (int64_t tile0 = 0; tile0 < n; tile0 += TILE) {
+        // tile items: the fold itself on the first pass, the previous pass's output after
+        auto fetch = [&](int64_t tile0, uint64_t (&it)[kSortItems]) {
             const int64_t seg0 = tile0 + (int64_t)wave * 64 * kSortItems;
-            uint64_t item[kSortItems];
+#pragma unroll
+            for (int e = 0; e < kSortItems; ++e) {
+                const int64_t idx = seg0 + e * 64 + lane;
+                if (idx < n) {
+                    it[e] = (pass == 0) ? (((uint64_t)phase_key(phase_of(t[idx], period)) << 32) | (uint32_t)idx)
+                                        : src[idx];
+                } else {
+                    it[e] = 0ull;
+                }
+            }
+        };
+        uint64_t item[kSortItems], nxt[PREFETCH ? kSortItems : 1];
+        fetch(0, item);
+        for (int64_t tile0 = 0; tile0 < n; tile0 += TILE) {
+            if constexpr (!PREFETCH) {
+                if (tile0 > 0) fetch(tile0, item);
+            }
+            const int64_t seg0 = tile0 + (int64_t)wave * 64 * kSortItems;
             uint32_t dig[kSortItems], rnk[kSortItems];
 #pragma unroll
             for (int e = 0; e < kSortItems; ++e) {
                 const int64_t idx = seg0 + e * 64 + lane;
                 const bool active = idx < n;
-                item[e] = active ? src[idx] : 0ull;
                 const uint32_t d = active ? (uint32_t)(item[e] >> shift) & 255u : 0u;
                 uint64_t peers = __ballot(active);
 #pragma unroll
@@ -311,6 +379,9 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
                 rnk[e] = cnt + before;
                 dig[e] = d;
             }
+            if constexpr (PREFETCH) {
+                if (tile0 + TILE < n) fetch(tile0 + TILE, nxt);
+            }
             __syncthreads();
             if (tid < 256) {
                 uint32_t run = sh.dbase[tid];
@@ -326,19 +397,23 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
             for (int e = 0; e < kSortItems; ++e) {
                 const int64_t idx = seg0 + e * 64 + lane;
                 const uint32_t pos = sh.wcnt[wave][dig[e]] + rnk[e];
-                if (idx < n && pos < (uint32_t)n) dst[pos] = item[e];
+                if (idx < n && pos < (uint32_t)n) {
+                    dst[pos] = item[e];
+                    if (pass == 2 && gather) pad_store(po, n, pos, (uint32_t)item[e]);
+                }
             }
             __syncthreads();
             for (int k = tid; k < W * 256; k += NT) (&sh.wcnt[0][0])[k] = 0;
             __syncthreads();
+            if constexpr (PREFETCH) {
+#pragma unroll
+                for (int e = 0; e < kSortItems; ++e) item[e] = nxt[e];
+            }
         }
-        uint64_t* tmp = src;
-        src = dst;
-        dst = tmp;
     }
-    // src == A: order by 32-bit key, equal keys in input order.  Equal 32-bit
-    // keys may hide different phases: order each run by the full FP64 phase,
-    // then input index (insertion sort; runs are rare and short).
+    // A: order by 24-bit key, equal keys in input order.  Equal keys may hide
+    // different phases: order each run by the full FP64 phase, then input
+    // index (insertion sort; runs are short), and rewrite its padded copies.
     for (int64_t k = tid; k + 1 < n; k += NT) {
         const uint32_t kk = (uint32_t)(A[k] >> 32);
         if (kk == (uint32_t)(A[k + 1] >> 32) && (k == 0 || (uint32_t)(A[k - 1] >> 32) != kk)) {
@@ -353,36 +428,19 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
                 }
                 A[y] = v;
             }
+            if (gather)
+                for (int64_t x = k; x <= e; ++x) pad_store(po, n, x, (uint32_t)A[x]);
         }
     }
     __syncthreads();
 }
 
-// Padding (Sect. 2.3.2): residuals (and weights) in phase order for npad
-// = n + D_max positions, position k holding point k mod n; with the moving-
-// average depth, prefix sums of 1 - y over the same positions.
+// Moving-average depth: prefix sums of 1 - y over the npad padded positions
+// (position k holding sorted point k mod n), from the final order in A.
 template <int NT>
-__device__ void pad_gather(const uint64_t* __restrict__ A, int64_t n, int64_t npad, const double* __restrict__ r,
-                           const double* __restrict__ w, const int64_t* __restrict__ u, void* rpad, void* wpad,
+__device__ void pad_prefix(const uint64_t* __restrict__ A, int64_t n, int64_t npad, const int64_t* __restrict__ u,
                            void* pfx, bool f32, SortShared<NT>& sh) {
     const int tid = threadIdx.x;
-    if (f32) {
-        float* rp = (float*)rpad;
-        float* wp = (float*)wpad;
-        for (int64_t k = tid; k < npad; k += NT) {
-            const uint32_t idx = (uint32_t)A[k < n ? k : k - n];
-            rp[k] = (float)r[idx];
-            if (wp) wp[k] = (float)w[idx];
-        }
-    } else {
-        double* rp = (double*)rpad;
-        double* wp = (double*)wpad;
-        for (int64_t k = tid; k < npad; k += NT) {
-            const uint32_t idx = (uint32_t)A[k < n ? k : k - n];
-            rp[k] = r[idx];
-            if (wp) wp[k] = w[idx];
-        }
-    }
     if (!pfx) return;
     const int64_t chunk = (npad + NT - 1) / NT;
     const int64_t c0 = (int64_t)tid * chunk, c1 = min(npad, c0 + chunk);
@@ -487,15 +545,16 @@ __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
     const int64_t n = a.n;
     uint64_t* A = a.keys_a + (size_t)pl * n;
     uint64_t* B = a.keys_b + (size_t)pl * n;
-    fold_sort_core<kSortThreads>(a.t, n, period, A, B, sh);
     if (threadIdx.x == 0) sh.dpad = max_points(n, period, a.durations, a.nd, a.prm);
     __syncthreads();
     const int64_t npad = n + sh.dpad;
     const size_t es = a.f32 ? sizeof(float) : sizeof(double);
     const size_t ps = a.f32 ? sizeof(float2) : sizeof(__int128);
-    pad_gather<kSortThreads>(A, n, npad, a.r, a.w, a.u, (char*)a.rpad + (size_t)pl * a.pstride * es,
-                             a.wpad ? (char*)a.wpad + (size_t)pl * a.pstride * es : nullptr,
-                             a.pfx ? (char*)a.pfx + (size_t)pl * (a.pstride + 1) * ps : nullptr, a.f32 != 0, sh);
+    PadOut po{a.r, a.w, a.rpad ? (char*)a.rpad + (size_t)pl * a.pstride * es : nullptr,
+              a.wpad ? (char*)a.wpad + (size_t)pl * a.pstride * es : nullptr, npad, a.f32 != 0};
+    fold_sort_core<kSortThreads, true>(a.t, n, period, A, B, po, sh);
+    pad_prefix<kSortThreads>(A, n, npad, a.u, a.pfx ? (char*)a.pfx + (size_t)pl * (a.pstride + 1) * ps : nullptr,
+                             a.f32 != 0, sh);
     if (a.perm_out) {
         int32_t* po = a.perm_out + (size_t)pl * n;
         for (int64_t k = threadIdx.x; k < n; k += kSortThreads) po[k] = (int32_t)(uint32_t)A[k];
@@ -504,27 +563,36 @@ __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
 
 // ------------------------------------------------------------------------
 // Template table: row D holds the D-point ideal transit, zero-padded to a
-// multiple of 32, so any (period, duration) item reads its template as a
-// uniform stream through the scalar cache.  FP32C keeps a float copy.  With
+// multiple of 32 and preceded by 32 zeros (the last row is followed by 32
+// more), so any (period, duration) item reads its template as a uniform
+// stream through the scalar cache, and a 16-point read that starts up to 31
+// points before the row or ends up to 31 points after it sees zeros there.  FP32C keeps a float copy.  With
 // constant weights the per-window b = sum_k w s_k^2 and the template sum
 // s1 = sum_k s_k depend on D only; they are summed once per D, in FP64 and
 // in the same sequential order as a per-window evaluation.
 
+constexpr int kTGuard = 32;
 __host__ __device__ __forceinline__ int64_t trow_off(int64_t d) {
     const int64_t m = d - 1, a = m / 32, b = m % 32;
-    return 32 * (16 * a * (a + 1) + (a + 1) * b);
+    return 32 * (16 * a * (a + 1) + (a + 1) * b) + kTGuard * d;
 }
 __host__ __device__ __forceinline__ int64_t rup32(int64_t d) { return (d + 31) & ~(int64_t)31; }
 
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
 
+// One block per D in [1, dcap]; table holds trow_off(dcap + 1) elements.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tmpl_table(const double* __restrict__ tm, int32_t nt, T* __restrict__ table) {
+__global__ __launch_bounds__(256) void k_tmpl_table(const double* __restrict__ tm, int32_t nt, int64_t dcap,
+                                                    T* __restrict__ table) {
     const int64_t d = (int64_t)blockIdx.x + 1;
     T* row = table + trow_off(d);
     const int64_t w = rup32(d);
     for (int64_t k = threadIdx.x; k < w; k += 256) row[k] = (k < d) ? (T)resample(tm, nt, d, k) : (T)0;
+    if (threadIdx.x < kTGuard) {
+        row[(int)threadIdx.x - kTGuard] = (T)0;
+        if (d == dcap) row[w + threadIdx.x] = (T)0;
+    }
 }
 
 // b_D = sum_k fma(w, s_k^2, .) and s1_D = sum_k s_k, sequential in k, over
@@ -577,6 +645,12 @@ struct SlideArgs {
     const double* s1sum;     // [D] template sums
     ItemBest* items;         // [bp][nd][ntiles]
     int32_t ntiles;          // window tiles per unit-stride item
+    // Strided items: wave tasks in launch order.
+    int32_t* toff;           // [bp nd + 1] first task of item (jrev bp + pl); last = total
+    int32_t* tmap;           // [bp nd kTaskMax] item of task
+    ItemBest* sb;            // [bp nd kTaskMax] best of task
+    uint32_t* queue;         // [2] next task, total
+    int32_t rmax;            // most windows per lane (the FP32C rule keeps it at 4)
 };
 
 struct Best {
@@ -782,10 +856,26 @@ __device__ Best slide_unit_tile(const SlideItem& si, int64_t i0, T* x_sh, T* xw_
         const int kc = (int)min((int64_t)kKC, si.dpad - k0);
         __syncthreads();
         const int nx = kTile + kc + kR;
-        for (int e = tid; e < nx; e += kSlideThreads) {
-            const int64_t g = i0 + k0 + e;
-            x_sh[xpad<T>(e)] = (g < si.limit) ? rp[g] : (T)0;
-            if (VARW) xw_sh[xpad<T>(e)] = (g < si.limit) ? wp[g] : (T)0;
+        {
+            // all of this lane's loads in flight before the first LDS write
+            constexpr int kPer = (kXs + kSlideThreads - 1) / kSlideThreads;
+            T v[kPer], vw[VARW ? kPer : 1];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int e = tid + q * kSlideThreads;
+                const int64_t g = i0 + k0 + e;
+                const bool ok = e < nx && g < si.limit;
+                v[q] = ok ? rp[g] : (T)0;
+                if constexpr (VARW) vw[q] = ok ? wp[g] : (T)0;
+            }
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int e = tid + q * kSlideThreads;
+                if (e < nx) {
+                    x_sh[xpad<T>(e)] = v[q];
+                    if constexpr (VARW) xw_sh[xpad<T>(e)] = vw[q];
+                }
+            }
         }
         __syncthreads();
         if (!busy) continue;
@@ -806,92 +896,190 @@ __device__ Best slide_unit_tile(const SlideItem& si, int64_t i0, T* x_sh, T* xw_
     return best;
 }
 
-// Strided T0 grid (stride >= 2): one window per lane, each wave working on
-// its own 64 windows through a wave-private LDS tile.  Small strides stage
-// the contiguous span the 64 windows cover (each point read once); large
-// strides stage each window's next 32 points as a transposed 64 x 32 tile
-// (coalesced reads of 32-point runs).  The template is a uniform stream.
-constexpr int kSTC = 32;                            // template points per tile step (transposed mode)
-constexpr int kSPitch = kSTC + 1;
-constexpr int kSTile = 64 * kSPitch;                // elements per wave tile
+// Strided T0 grid (stride s >= 2).  A wave works on a run of windows; each
+// lane owns R consecutive windows m, m + 1, ..., m + R - 1, which start s
+// points apart, so one curve point x[m s + j] serves all of them: window r
+// takes it with template point j - r s.  The lane walks j upward over its
+// own contiguous run of the padded curve in chunks of 16 (the next chunk is
+// loaded while this one is used); window r skips the chunks outside
+// [r s, r s + D) and reads zeros from the table guards in the two partial
+// ones (x * 0 leaves the running sum unchanged exactly), so every window
+// still sums its D products in ascending template order.
+constexpr int kSC = 16;                             // j steps per chunk
+constexpr int kTaskMax = 16;                        // wave tasks per strided item
 
-template <typename T, bool VARW, bool MEAN>
-__device__ Best slide_strided_item(const SlideItem& si, T* tiles, T* tilesw) {
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int64_t n = si.n, D = si.D, s = si.stride;
-    const int64_t nw = (n + s - 1) / s;
-    const T* __restrict__ rp = (const T*)si.rp;
-    const T* __restrict__ wp = (const T*)si.wp;
-    const cptr<T> trow = (cptr<T>)si.trow;
-    T* tl = tiles + wave * kSTile;
-    T* tw = VARW ? tilesw + wave * kSTile : nullptr;
-    // Contiguous mode: the 64 windows of a group span 63 s + TCu points.
-    const int64_t tcu = (kSTile - 63 * s) & ~(int64_t)31;
-    const bool contiguous = tcu >= 32;
-    const int64_t tc = contiguous ? tcu : kSTC;
-    Best best{-INFINITY, 0.0, -1};
-    __syncthreads();
-    for (int64_t g0 = (int64_t)wave * 64; g0 < nw; g0 += kSlideThreads) {
-        const int64_t m = g0 + lane;
-        const bool active = m < nw;
-        const int64_t i = m * s;
-        const int64_t ibase = g0 * s;
-        double c = 0.0, bv = 0.0;
-        for (int64_t k0 = 0; k0 < si.dpad; k0 += tc) {
-            const int kc = (int)min(tc, si.dpad - k0);
-            if (contiguous) {
-                const int64_t span = 63 * s + kc;
-                for (int64_t e = lane; e < span; e += 64) {
-                    const int64_t gsrc = ibase + k0 + e;
-                    tl[e] = (gsrc < si.limit) ? rp[gsrc] : (T)0;
-                    if (VARW) tw[e] = (gsrc < si.limit) ? wp[gsrc] : (T)0;
-                }
-            } else {
-                const int e = lane & 31;
-                for (int r = 0; r < 32; ++r) {
-                    const int seg = 2 * r + (lane >> 5);
-                    const int64_t mm = g0 + seg;
-                    const int64_t gsrc = mm * s + k0 + e;
-                    const bool ok = mm < nw && gsrc < si.limit;
-                    tl[seg * kSPitch + e] = ok ? rp[gsrc] : (T)0;
-                    if (VARW) tw[seg * kSPitch + e] = ok ? wp[gsrc] : (T)0;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const T* xl = contiguous ? tl + lane * s : tl + lane * kSPitch;
-            const T* xw = VARW ? (contiguous ? tw + lane * s : tw + lane * kSPitch) : nullptr;
-            const cptr<T> t = trow + k0;
-            for (int kb = 0; kb < kc; kb += kSTC) {
-                T cb = (sizeof(T) == 8) ? (T)c : (T)0;
-                T bb = (sizeof(T) == 8) ? (T)bv : (T)0;
-#pragma unroll
-                for (int kk = 0; kk < kSTC; ++kk) {
-                    const T sv = t[kb + kk];
-                    cb = fma(xl[kb + kk], sv, cb);
-                    if (VARW) bb = fma(xw[kb + kk], sv * sv, bb);
-                }
-                if constexpr (sizeof(T) == 8) {
-                    c = cb;
-                    bv = bb;
-                } else {
-                    c += (double)cb;
-                    bv += (double)bb;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-        if (active) {
-            double dchi2, depth;
-            fit<MEAN>(c, VARW ? bv : si.bconst, window_deficit<T, MEAN>(si.pf, i, D), si.s1, dchi2, depth);
-            consider(best, dchi2, depth, i);
+// Windows per lane: the largest of 8, 4, 2 (at most rmax) that still gives
+// `fill` lanes a window each, when consecutive windows overlap (s < D);
+// else 1.
+__host__ __device__ __forceinline__ int strided_r(int64_t nw, int64_t s, int64_t d, int64_t fill, int rmax) {
+    if (s >= d) return 1;
+    if (rmax >= 8 && nw >= 8 * fill) return 8;
+    if (rmax >= 4 && nw >= 4 * fill) return 4;
+    if (nw >= 2 * fill) return 2;
+    return 1;
+}
+
+// First-best over the 64 lanes (largest dchi2, then smallest start).
+__device__ __forceinline__ Best wave_best(Best best) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double od = __shfl_xor(best.dchi2, off);
+        const double op = __shfl_xor(best.depth, off);
+        const long long oi = __shfl_xor((long long)best.start, off);
+        const bool take = (od > best.dchi2) || (od == best.dchi2 && oi >= 0 && (best.start < 0 || oi < best.start));
+        if (take) {
+            best.dchi2 = od;
+            best.depth = op;
+            best.start = oi;
         }
     }
     return best;
+}
+
+// 16 points of a lane's run from index c0 on; points at or past `avail`
+// (the end of the padded curve) read as zero.
+template <typename T>
+__device__ __forceinline__ void run_chunk(T (&v)[kSC], const T* __restrict__ p, int64_t c0, int64_t avail) {
+    if (c0 + kSC <= avail) {
+#pragma unroll
+        for (int u = 0; u < kSC; ++u) v[u] = p[c0 + u];
+    } else {
+#pragma unroll
+        for (int u = 0; u < kSC; ++u) {
+            const bool ok = c0 + u < avail;
+            const T val = p[ok ? c0 + u : 0];
+            v[u] = ok ? val : (T)0;
+        }
+    }
+}
+
+template <typename T, bool VARW, int R>
+__device__ __forceinline__ void strided_chunk(double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
+                                              const T (&xw)[VARW ? kSC : 1], cptr<T> trow, int64_t c0, int64_t s,
+                                              int64_t D) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t klo = c0 - (int64_t)r * s;     // template index of x[0] for window r
+        if (klo > -kSC && klo < D) {
+            const cptr<T> t = trow + klo;
+            if constexpr (sizeof(T) == 8) {
+#pragma unroll
+                for (int u = 0; u < kSC; ++u) {
+                    acc[r] = fma((double)x[u], (double)t[u], acc[r]);
+                    if constexpr (VARW) bacc[r] = fma((double)xw[u], (double)(t[u] * t[u]), bacc[r]);
+                }
+            } else {
+                T ca = (T)0, cb = (T)0;
+#pragma unroll
+                for (int u = 0; u < kSC; ++u) {
+                    ca = fma(x[u], t[u], ca);
+                    if constexpr (VARW) cb = fma(xw[u], t[u] * t[u], cb);
+                }
+                acc[r] += (double)ca;
+                if constexpr (VARW) bacc[r] += (double)cb;
+            }
+        }
+    }
+}
+
+// Windows [m_lo, m_hi) of one item on one wave; returns the wave's first
+// best on every lane.  DB: load the next chunk while this one is used.
+template <typename T, bool VARW, bool MEAN, int R, bool DB>
+__device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi) {
+    const int lane = threadIdx.x & 63;
+    const int64_t s = si.stride, D = si.D;
+    const cptr<T> trow = (cptr<T>)si.trow;
+    const int64_t J = D + (R - 1) * s;              // j steps of a lane
+    Best best{-INFINITY, 0.0, -1};
+    for (int64_t g0 = m_lo; g0 < m_hi; g0 += 64 * R) {
+        const int64_t ml = g0 + (int64_t)lane * R;
+        const int64_t base = min(ml, m_hi - 1) * s;  // lanes past the range re-read a valid run
+        const int64_t avail = si.limit - base;
+        const T* __restrict__ xp = (const T*)si.rp + base;
+        const T* __restrict__ xq = VARW ? (const T*)si.wp + base : nullptr;
+        double acc[R], bacc[VARW ? R : 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int r = 0; r < (VARW ? R : 1); ++r) bacc[r] = 0.0;
+        if constexpr (!DB) {
+            T va[kSC], wa[VARW ? kSC : 1];
+            for (int64_t c0 = 0; c0 < J; c0 += kSC) {
+                run_chunk(va, xp, c0, avail);
+                if constexpr (VARW) run_chunk(wa, xq, c0, avail);
+                strided_chunk<T, VARW, R>(acc, bacc, va, wa, trow, c0, s, D);
+            }
+        } else {
+            T va[kSC], vb[kSC], wa[VARW ? kSC : 1], wb[VARW ? kSC : 1];
+            run_chunk(va, xp, 0, avail);
+            if constexpr (VARW) run_chunk(wa, xq, 0, avail);
+            for (int64_t c0 = 0; c0 < J; c0 += 2 * kSC) {
+                const bool more = c0 + kSC < J;
+                if (more) {
+                    run_chunk(vb, xp, c0 + kSC, avail);
+                    if constexpr (VARW) run_chunk(wb, xq, c0 + kSC, avail);
+                }
+                strided_chunk<T, VARW, R>(acc, bacc, va, wa, trow, c0, s, D);
+                if (!more) break;
+                if (c0 + 2 * kSC < J) {
+                    run_chunk(va, xp, c0 + 2 * kSC, avail);
+                    if constexpr (VARW) run_chunk(wa, xq, c0 + 2 * kSC, avail);
+                }
+                strided_chunk<T, VARW, R>(acc, bacc, vb, wb, trow, c0 + kSC, s, D);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t m = ml + r;
+            if (m < m_hi) {
+                const int64_t i = m * s;
+                double dchi2, depth;
+                fit<MEAN>(acc[r], VARW ? bacc[r] : si.bconst, window_deficit<T, MEAN>(si.pf, i, D), si.s1, dchi2,
+                          depth);
+                consider(best, dchi2, depth, i);
+            }
+        }
+    }
+    return wave_best(best);
+}
+
+template <typename T, bool VARW, bool MEAN, int RMAX, bool DB>
+__device__ Best strided_windows_r(int R, const SlideItem& si, int64_t m_lo, int64_t m_hi) {
+    switch (R) {
+        case 8:
+            if constexpr (RMAX >= 8) return strided_windows<T, VARW, MEAN, 8, DB>(si, m_lo, m_hi);
+            [[fallthrough]];
+        case 4: return strided_windows<T, VARW, MEAN, 4, DB>(si, m_lo, m_hi);
+        case 2: return strided_windows<T, VARW, MEAN, 2, DB>(si, m_lo, m_hi);
+        default: return strided_windows<T, VARW, MEAN, 1, DB>(si, m_lo, m_hi);
+    }
+}
+
+// Wave tasks of a strided item: its window groups (64 R windows each) split
+// into at most kTaskMax contiguous runs.
+struct StridedSplit {
+    int R;
+    int64_t nw, groups;
+    int ntask;
+};
+
+__host__ __device__ __forceinline__ StridedSplit strided_split(int64_t n, int64_t d, int64_t s, int64_t fill,
+                                                               int64_t max_tasks, int rmax) {
+    StridedSplit sp;
+    sp.nw = (n + s - 1) / s;
+    sp.R = strided_r(sp.nw, s, d, fill, rmax);
+    const int64_t lanes = (sp.nw + sp.R - 1) / sp.R;
+    sp.groups = (lanes + 63) / 64;
+    sp.ntask = (int)min(sp.groups, max_tasks);
+    return sp;
+}
+
+// Windows of task t of ntask.
+__host__ __device__ __forceinline__ void strided_task_range(const StridedSplit& sp, int t, int64_t& m_lo,
+                                                            int64_t& m_hi) {
+    const int64_t g_lo = sp.groups * t / sp.ntask, g_hi = sp.groups * (t + 1) / sp.ntask;
+    const int64_t per = 64 * (int64_t)sp.R;
+    m_lo = min(sp.nw, g_lo * per);
+    m_hi = min(sp.nw, g_hi * per);
 }
 
 template <typename T, bool MEAN>
@@ -930,18 +1118,88 @@ __global__ __launch_bounds__(kSlideThreads) void k_slide_unit(SlideArgs a) {
     store_best(b, a, it, min((int64_t)kTile, a.n - i0), a.ntiles);
 }
 
-template <typename T, bool VARW, bool MEAN>
-__global__ __launch_bounds__(kSlideThreads) void k_slide_strided(SlideArgs a) {
-    __shared__ T tile[(kSlideThreads / 64) * kSTile];
-    __shared__ T tilew[VARW ? (kSlideThreads / 64) * kSTile : 1];
-    __shared__ Best red[kSlideThreads / 64];
-    const ItemInfo it = item_info(a, 1);
-    if (!it.valid || it.stride == 1) return;     // the unit-stride kernel writes those items
-    const SlideItem si = make_item<T, MEAN>(a, it, VARW);
-    const Best b = block_best(slide_strided_item<T, VARW, MEAN>(si, tile, tilew), red);
-    store_best(b, a, it, (a.n + it.stride - 1) / it.stride, 1);
+constexpr int kPlanThreads = 1024;
+
+// Lists the wave tasks of the strided items of one launch in launch order
+// (longest duration first): toff[idx] is the first task of item idx = jrev
+// bp + pl, toff[bp nd] the total; tmap[task] = idx.  Resets the task queue.
+__global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
+    __shared__ int32_t part[kPlanThreads];
+    const int tid = threadIdx.x;
+    const int64_t items = (int64_t)a.bp * a.nd;
+    const int64_t per = (items + kPlanThreads - 1) / kPlanThreads;
+    const int64_t lo = min(items, (int64_t)tid * per), hi = min(items, lo + per);
+    auto count = [&](int64_t idx) -> int {
+        const int jrev = (int)(idx / a.bp);
+        const int pl = (int)(idx - (int64_t)jrev * a.bp);
+        const double period = a.periods[pl], dur = a.durations[a.nd - 1 - jrev];
+        if (!duration_valid(period, dur, a.prm)) return 0;
+        const int64_t d = points_in(a.n, period, dur);
+        const int64_t st = t0_stride(d, a.prm.dt0);
+        return st < 2 ? 0 : strided_split(a.n, d, st, 64, kTaskMax, a.rmax).ntask;
+    };
+    int32_t sum = 0;
+    for (int64_t idx = lo; idx < hi; ++idx) sum += count(idx);
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kPlanThreads; off <<= 1) {
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t o = part[tid] - sum;
+    for (int64_t idx = lo; idx < hi; ++idx) {
+        const int c = count(idx);
+        a.toff[idx] = o;
+        for (int t = 0; t < c; ++t) a.tmap[o + t] = (int32_t)idx;
+        o += c;
+    }
+    if (tid == kPlanThreads - 1) {
+        a.toff[items] = part[tid];
+        a.queue[0] = 0u;
+        a.queue[1] = (uint32_t)part[tid];
+    }
 }
 
+// Persistent: every wave pops wave tasks until the list is exhausted.
+template <typename T, bool VARW, bool MEAN>
+__global__ __launch_bounds__(kSlideThreads) void k_slide_strided(SlideArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.queue[1]);
+    for (;;) {
+        // Every lane takes part in the pop (lane 0 adds 1, the rest 0) so no
+        // divergent branch feeds the broadcast of lane 0's ticket.
+        const uint32_t ticket = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
+        const uint32_t task = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
+        if (task >= total) break;
+        const int32_t idx = __builtin_amdgcn_readfirstlane(a.tmap[task]);
+        const int t = (int)task - __builtin_amdgcn_readfirstlane(a.toff[idx]);
+        ItemInfo it;
+        const int jrev = idx / a.bp;
+        it.pl = idx - jrev * a.bp;
+        it.j = a.nd - 1 - jrev;
+        it.tile = 0;
+        it.valid = true;
+        it.period = a.periods[it.pl];
+        it.d = points_in(a.n, it.period, a.durations[it.j]);
+        it.stride = t0_stride(it.d, a.prm.dt0);
+        const SlideItem si = make_item<T, MEAN>(a, it, VARW);
+        const StridedSplit sp = strided_split(a.n, it.d, it.stride, 64, kTaskMax, a.rmax);
+        int64_t m_lo, m_hi;
+        strided_task_range(sp, t, m_lo, m_hi);
+        const Best b = strided_windows_r<T, VARW, MEAN, 8, true>(sp.R, si, m_lo, m_hi);
+        if (lane == 0) {
+            ItemBest* o = a.sb + task;
+            o->dchi2 = b.dchi2;
+            o->depth = b.depth;
+            o->start = (int32_t)b.start;
+            o->d = (int32_t)it.d;
+            o->evals = (int32_t)(m_hi - m_lo);
+            o->ntiles = 0;
+        }
+    }
+}
 // ------------------------------------------------------------------------
 // Per-period reduction over durations and the T0 of the best window.
 
@@ -953,6 +1211,8 @@ struct ReduceArgs {
     int32_t nd;
     const ItemBest* items;
     int32_t ntiles;
+    const int32_t* toff;     // strided items: task slots, or null
+    const ItemBest* sb;
     const uint64_t* keys_a;
     const uint64_t* misc;
     uint64_t* misc_rw;
@@ -972,8 +1232,15 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
         double best = -INFINITY, bdepth = 0.0;
         int bj = -1, bi = -1, bd = 0;
         for (int j = 0; j < a.nd; ++j) {
+            const int64_t idx = (int64_t)(a.nd - 1 - j) * a.bp + pl;
             const ItemBest* slots = a.items + ((size_t)pl * a.nd + j) * a.ntiles;
-            const int nt = min(max(slots[0].ntiles, 0), a.ntiles);
+            int nt;
+            if (a.toff && a.toff[idx + 1] > a.toff[idx]) {
+                slots = a.sb + a.toff[idx];
+                nt = a.toff[idx + 1] - a.toff[idx];
+            } else {
+                nt = min(max(slots[0].ntiles, 0), a.ntiles);
+            }
             for (int t = 0; t < nt; ++t) {
                 const ItemBest b = slots[t];
                 if (b.start < 0) continue;
@@ -1379,7 +1646,7 @@ struct BatchShared {
 };
 
 template <typename T, bool MEAN, bool ANYVARW>
-__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
+__global__ __launch_bounds__(kBatchThreads, 2) void k_batch(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ BatchShared bs;
     SortShared<kBatchThreads>& ssh = *reinterpret_cast<SortShared<kBatchThreads>*>(dyn);
@@ -1397,7 +1664,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
         __syncthreads();
         if (tid == 0) bs.item = (int64_t)atomicAdd(a.queue, 1ull);
         __syncthreads();
-        const int64_t item = bs.item;
+        const int64_t item = ((int64_t)__builtin_amdgcn_readfirstlane((int)(bs.item >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bs.item);
         if (item >= stop) break;
         // queue position -> (curve, period)
         int lo = 0, hi = a.nc;
@@ -1414,12 +1682,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
         const bool varw = ANYVARW && (m[kWminBits] != m[kWmaxBits]);
         const double wc = __longlong_as_double((long long)m[kWminBits]);
 
-        fold_sort_core<kBatchThreads>(a.t + o0, n, period, A, B, ssh);
         if (tid == 0) bs.dpad = max_points(n, period, a.durations, a.nd, a.prm);
         __syncthreads();
         const int64_t npad = n + bs.dpad;
-        pad_gather<kBatchThreads>(A, n, npad, a.r + o0, a.w + o0, a.u + o0, rpad, varw ? wpad : nullptr, pfx,
-                                  sizeof(T) == 4, ssh);
+        const PadOut po{a.r + o0, a.w + o0, rpad, varw ? wpad : nullptr, npad, sizeof(T) == 4};
+        fold_sort_core<kBatchThreads, false>(a.t + o0, n, period, A, B, po, ssh);
+        pad_prefix<kBatchThreads>(A, n, npad, a.u + o0, pfx, sizeof(T) == 4, ssh);
         // Constant-weight b per duration: one sequential chain per lane.
         if (!varw) {
             for (int j = tid; j < a.nd; j += kBatchThreads) {
@@ -1470,11 +1738,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchArgs a) {
                     if (tb.dchi2 > jb.dchi2) jb = tb;
                 }
             } else {
-                T* tl = reinterpret_cast<T*>(dyn);
-                T* tw = tl + (kBatchThreads / 64) * kSTile;
+                // the item's window groups split into one contiguous run per wave
+                const int wave = tid >> 6;
+                // At most 4 windows per lane: the megakernel's other phases already hold many registers.
+                // FP32C flushes its float partial sums at chunk boundaries that depend on the window's
+                // place in its lane, so it uses the single-curve rule (fill one wave, R <= 4) to give
+                // identical results.
+                const StridedSplit sp = strided_split(n, si.D, si.stride, sizeof(T) == 4 ? 64 : kBatchThreads,
+                                                      kBatchThreads / 64, 4);
+                int64_t m_lo = 0, m_hi = 0;
+                if (wave < sp.ntask) strided_task_range(sp, wave, m_lo, m_hi);
                 Best lb;
-                if (ANYVARW && varw) lb = slide_strided_item<T, ANYVARW, MEAN>(si, tl, tw);
-                else lb = slide_strided_item<T, false, MEAN>(si, tl, tw);
+                if (ANYVARW && varw) lb = strided_windows_r<T, ANYVARW, MEAN, 4, false>(sp.R, si, m_lo, m_hi);
+                else lb = strided_windows_r<T, false, MEAN, 4, false>(sp.R, si, m_lo, m_hi);
                 jb = block_best(lb, bs.red);
             }
             if (jb.dchi2 > pbest.dchi2) {
@@ -1596,7 +1872,7 @@ struct Plan {
     int32_t bp, ntiles;
     bool varw, mean, f32;
     size_t esize, psize;     // bytes per padded-curve element and per prefix element
-    size_t off_a, off_b, off_r, off_w, off_pf, off_items, per_batch;
+    size_t off_a, off_b, off_r, off_w, off_pf, off_items, off_toff, off_tmap, off_sb, off_queue, per_batch;
 };
 
 Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm, bool varw) {
@@ -1614,7 +1890,8 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     p.pstride = ((n + dcap + 63) / 64) * 64;
     size_t per = 2 * sizeof(uint64_t) * (size_t)n + p.esize * (size_t)p.pstride +
                  (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
-                 sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles + 1024;
+                 sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles +
+                 (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kTaskMax + 1024;
     const size_t budget = (size_t)24 << 30;
     int64_t bp = (int64_t)(budget / per);
     bp = std::max<int64_t>(1, std::min<int64_t>(bp, 8192));
@@ -1636,25 +1913,43 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     if (p.mean) o = align256(o + p.psize * (size_t)(p.pstride + 1) * bp);
     p.off_items = o;
     o = align256(o + sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles * bp);
+    p.off_toff = o;
+    o = align256(o + sizeof(int32_t) * ((size_t)nd * bp + 1));
+    p.off_tmap = o;
+    o = align256(o + sizeof(int32_t) * (size_t)nd * kTaskMax * bp);
+    p.off_sb = o;
+    o = align256(o + sizeof(ItemBest) * (size_t)nd * kTaskMax * bp);
+    p.off_queue = o;
+    o = align256(o + 2 * sizeof(uint32_t));
     p.per_batch = o;
     return p;
 }
 
+// Unit-stride tiles, then (strided T0 grids) the wave-task list and the
+// persistent strided kernel, sized to fill every CU.
 template <typename T, bool VARW, bool MEAN>
-void launch_slides(const SlideArgs& la, unsigned grid, unsigned grid_items, bool strided, hipStream_t s) {
+void launch_slides(const SlideArgs& la, unsigned grid, bool strided, int num_cus, hipStream_t s) {
     k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
-    if (strided) k_slide_strided<T, VARW, MEAN><<<grid_items, kSlideThreads, 0, s>>>(la);
+    if (strided) {
+        k_strided_plan<<<1, kPlanThreads, 0, s>>>(la);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slide_strided<T, VARW, MEAN>, kSlideThreads, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        k_slide_strided<T, VARW, MEAN><<<(unsigned)(per_cu * std::max(num_cus, 1)), kSlideThreads, 0, s>>>(la);
+    }
 }
 
 template <typename T>
-void launch_slides(const SlideArgs& la, unsigned grid, unsigned grid_items, bool strided, bool varw, bool mean,
+void launch_slides(const SlideArgs& la, unsigned grid, bool strided, bool varw, bool mean, int num_cus,
                    hipStream_t s) {
     if (varw) {
-        if (mean) launch_slides<T, true, true>(la, grid, grid_items, strided, s);
-        else launch_slides<T, true, false>(la, grid, grid_items, strided, s);
+        if (mean) launch_slides<T, true, true>(la, grid, strided, num_cus, s);
+        else launch_slides<T, true, false>(la, grid, strided, num_cus, s);
     } else {
-        if (mean) launch_slides<T, false, true>(la, grid, grid_items, strided, s);
-        else launch_slides<T, false, false>(la, grid, grid_items, strided, s);
+        if (mean) launch_slides<T, false, true>(la, grid, strided, num_cus, s);
+        else launch_slides<T, false, false>(la, grid, strided, num_cus, s);
     }
 }
 
@@ -1696,8 +1991,8 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     double* s1sum = (double*)((char*)ctx->table.ptr + off_s1);
     {
         StageTimer tm(ctx, kStagePrep);
-        if (pl.f32) k_tmpl_table<float><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, (float*)table);
-        else k_tmpl_table<double><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, (double*)table);
+        if (pl.f32) k_tmpl_table<float><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, pl.dcap, (float*)table);
+        else k_tmpl_table<double><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, pl.dcap, (double*)table);
         if (pl.f32) k_tmpl_sums<float><<<(unsigned)((pl.dcap + 63) / 64), 64, 0, s>>>((const float*)table, pl.dcap, misc, bsum, s1sum);
         else k_tmpl_sums<double><<<(unsigned)((pl.dcap + 63) / 64), 64, 0, s>>>((const double*)table, pl.dcap, misc, bsum, s1sum);
     }
@@ -1710,6 +2005,10 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     void* wpad = varw ? (void*)(bb + pl.off_w) : nullptr;
     void* pfx = pl.mean ? (void*)(bb + pl.off_pf) : nullptr;
     ItemBest* items = (ItemBest*)(bb + pl.off_items);
+    int32_t* toff = (int32_t*)(bb + pl.off_toff);
+    int32_t* tmap = (int32_t*)(bb + pl.off_tmap);
+    ItemBest* sb = (ItemBest*)(bb + pl.off_sb);
+    uint32_t* queue = (uint32_t*)(bb + pl.off_queue);
     const bool strided = a.prm.dt0 > 0.0;
 
     for (int32_t p0 = 0; p0 < a.n_periods; p0 += pl.bp) {
@@ -1721,15 +2020,15 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
             k_fold_sort<<<bp, kSortThreads, 0, s>>>(sa);
         }
         SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.prm, rpad, wpad, pfx, pl.pstride,
-                     misc, table, bsum, s1sum, items, pl.ntiles};
+                     misc, table, bsum, s1sum, items, pl.ntiles, toff, tmap, sb, queue, pl.f32 ? 4 : 8};
         const unsigned grid = (unsigned)bp * (unsigned)a.n_durations * (unsigned)pl.ntiles;
-        const unsigned grid_items = (unsigned)bp * (unsigned)a.n_durations;
         {
             StageTimer tm(ctx, kStageSlide);
-            if (pl.f32) launch_slides<float>(la, grid, grid_items, strided, varw, pl.mean, s);
-            else launch_slides<double>(la, grid, grid_items, strided, varw, pl.mean, s);
+            if (pl.f32) launch_slides<float>(la, grid, strided, varw, pl.mean, ctx->num_cus, s);
+            else launch_slides<double>(la, grid, strided, varw, pl.mean, ctx->num_cus, s);
         }
-        ReduceArgs ra{a.t, n, a.periods + p0, bp, a.n_durations, items, pl.ntiles, keys_a, misc, misc,
+        ReduceArgs ra{a.t, n, a.periods + p0, bp, a.n_durations, items, pl.ntiles, strided ? toff : nullptr, sb,
+                      keys_a, misc, misc,
                       a.chi2 + p0, a.best_dur + p0, a.best_start + p0, a.depth + p0, a.t0 + p0};
         {
             StageTimer tm(ctx, kStageReduce);
@@ -1751,8 +2050,7 @@ size_t batch_lds_bytes() {
     const size_t es = sizeof(T), mult = ANYVARW ? 2 : 1;
     const size_t sort = sizeof(SortShared<kBatchThreads>);
     const size_t unit = (size_t)xpad<T>(kXs) * es * mult;
-    const size_t strided = (size_t)(kBatchThreads / 64) * kSTile * es * mult;
-    return std::max(sort, std::max(unit, strided));
+    return std::max(sort, unit);
 }
 
 template <typename T, bool MEAN, bool ANYVARW>
@@ -1851,8 +2149,8 @@ hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& h) {
     {
         StageTimer tm(ctx, kStagePrep);
         k_prep_batch<<<nc, 256, 0, s>>>(d_off, h.t, h.y, h.dy, w, r, u, cmisc);
-        if (f32) k_tmpl_table<float><<<(unsigned)dcap, 256, 0, s>>>(h.tmpl, h.nt, (float*)ctx->table.ptr);
-        else k_tmpl_table<double><<<(unsigned)dcap, 256, 0, s>>>(h.tmpl, h.nt, (double*)ctx->table.ptr);
+        if (f32) k_tmpl_table<float><<<(unsigned)dcap, 256, 0, s>>>(h.tmpl, h.nt, dcap, (float*)ctx->table.ptr);
+        else k_tmpl_table<double><<<(unsigned)dcap, 256, 0, s>>>(h.tmpl, h.nt, dcap, (double*)ctx->table.ptr);
         if (f32) k_tmpl_s1<float><<<(unsigned)((dcap + 63) / 64), 64, 0, s>>>((const float*)ctx->table.ptr, dcap, s1sum);
         else k_tmpl_s1<double><<<(unsigned)((dcap + 63) / 64), 64, 0, s>>>((const double*)ctx->table.ptr, dcap, s1sum);
     }
@@ -1976,21 +2274,14 @@ hipError_t run_fold_sort(gtls_ctx* ctx, const double* t, int64_t n, const double
     gtls_params prm;
     gtls_params_default(&prm);
     const Plan pl = make_plan(n, n_periods, 1, prm, false);
-    // r/w/u are read by the padding step; give it a zeroed dummy curve.
-    const size_t off_r = 256, off_u = align256(off_r + 8 * (size_t)n);
-    hipError_t e = ensure(ctx, ctx->curve, align256(off_u + 8 * (size_t)n));
-    if (e != hipSuccess) return e;
-    char* cb = (char*)ctx->curve.ptr;
-    double* r = (double*)(cb + off_r);
-    int64_t* u = (int64_t*)(cb + off_u);
-    e = ensure(ctx, ctx->batch, pl.per_batch);
+    hipError_t e = ensure(ctx, ctx->batch, pl.per_batch);
     if (e != hipSuccess) return e;
     char* bb = (char*)ctx->batch.ptr;
     for (int32_t p0 = 0; p0 < n_periods; p0 += pl.bp) {
         const int32_t bp = std::min(pl.bp, n_periods - p0);
-        SortArgs sa{t, r, r, u, n, periods + p0, periods, 0, prm, (uint64_t*)(bb + pl.off_a),
-                    (uint64_t*)(bb + pl.off_b), bb + pl.off_r, nullptr, nullptr, pl.pstride,
-                    perm + (size_t)p0 * n, 0};
+        // permutation only: no padded copies, no prefix sums
+        SortArgs sa{t, nullptr, nullptr, nullptr, n, periods + p0, periods, 0, prm, (uint64_t*)(bb + pl.off_a),
+                    (uint64_t*)(bb + pl.off_b), nullptr, nullptr, nullptr, pl.pstride, perm + (size_t)p0 * n, 0};
         k_fold_sort<<<bp, kSortThreads, 0, s>>>(sa);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

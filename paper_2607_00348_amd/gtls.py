@@ -24,7 +24,7 @@ GTLS_DEPTH_WLS, GTLS_DEPTH_MEAN = 0, 1
 EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_default", "gtls_sync",
             "gtls_profile_enable", "gtls_profile_read",
             "tls_search", "tls_search_dev", "tls_search_batch", "tls_search_batch_dev", "tls_fold_sort",
-            "tls_sde", "gtls_period_grid_ofir",
+            "tls_sde", "tls_search_refined", "gtls_period_grid_ofir",
             "gtls_duration_grid", "gtls_template_quadratic", "gtls_cnn_num_params", "gtls_cnn_create",
             "gtls_cnn_destroy", "gtls_cnn_view", "gtls_cnn_forward", "gtls_cnn_gradients", "gtls_cnn_train_step",
             "gtls_cnn_get_params", "gtls_cnn_topk"]
@@ -110,6 +110,11 @@ def lib():
         L.tls_fold_sort.argtypes = [vp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _ip]
         L.tls_sde.restype = ctypes.c_int
         L.tls_sde.argtypes = [vp, _dp, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _ip]
+        L.tls_search_refined.restype = ctypes.c_int
+        L.tls_search_refined.argtypes = [vp, _dp, _dp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp,
+                                         ctypes.c_int32, _dp, ctypes.c_int32, ctypes.POINTER(gtls_params),
+                                         ctypes.c_int32, ctypes.POINTER(gtls_result),
+                                         ctypes.POINTER(ctypes.c_uint8)]
         L.gtls_period_grid_ofir.restype = ctypes.c_int
         L.gtls_period_grid_ofir.argtypes = [ctypes.c_double] * 6 + [_dp, ctypes.c_int32, _ip]
         L.gtls_duration_grid.restype = ctypes.c_int
@@ -240,6 +245,29 @@ def tls_search(ctx: Context, time, flux, dy, period_grid, duration_grid, tmpl,
                             len(tm), ctypes.byref(prm), ctypes.byref(res)), ctx.ptr)
     return SearchResult(chi2_null=res.chi2_null, best_period=res.best_period, sde_max=res.sde_max,
                         n_evals=res.n_evals, n_macs=res.n_macs, **out)
+
+
+def tls_search_refined(ctx: Context, time, flux, dy, period_grid, duration_grid, tmpl, n_refine: int,
+                       params: gtls_params | None = None):
+    """Two-stage search; returns (SearchResult, refined mask)."""
+    t, y, e = _f64(time), _f64(flux), _f64(dy)
+    per, dur, tm = _f64(period_grid), _f64(duration_grid), _f64(tmpl)
+    npd = len(per)
+    out = {k: np.empty(npd) for k in ("chi2", "depth", "t0", "sr", "sde_raw", "sde")}
+    out["best_dur"] = np.empty(npd, dtype=np.int32)
+    out["best_start"] = np.empty(npd, dtype=np.int32)
+    refined = np.zeros(npd, dtype=np.uint8)
+    res = gtls_result()
+    for k in ("chi2", "depth", "t0", "sr", "sde_raw", "sde"):
+        setattr(res, k, _p(out[k]))
+    res.best_dur = out["best_dur"].ctypes.data_as(_ip)
+    res.best_start = out["best_start"].ctypes.data_as(_ip)
+    prm = params if params is not None else gtls_params_default()
+    _check(lib().tls_search_refined(ctx.ptr, _p(t), _p(y), _p(e), len(t), _p(per), npd, _p(dur), len(dur), _p(tm),
+                                    len(tm), ctypes.byref(prm), int(n_refine), ctypes.byref(res),
+                                    refined.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))), ctx.ptr)
+    return (SearchResult(chi2_null=res.chi2_null, best_period=res.best_period, sde_max=res.sde_max,
+                         n_evals=res.n_evals, n_macs=res.n_macs, **out), refined.astype(bool))
 
 
 def tls_search_dev(ctx: Context, time, flux, dy, n: int, period_grid, n_periods: int, duration_grid,

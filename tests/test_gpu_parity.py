@@ -100,6 +100,8 @@ def test_sde_kernel_matches_oracle(ctx, oracle):
     (13, 30011, dict(dt0=0.1, cadence=0.002)),
     (14, 24000, dict(dt0=0.5, cadence=0.002, varying_dy=True)),
     (15, 20000, dict(dt0=0.3, cadence=0.002, depth_mode=1)),
+    (16, 8000, dict(dt0=1.5)),                                   # stride > D: windows do not overlap
+    (17, 6000, dict(dt0=1.0, depth_mode=1, varying_dy=True)),    # stride == D
 ])
 def test_random_curves_match_oracle(ctx, oracle, seed, n, kw):
     kw = dict(kw)
@@ -117,6 +119,26 @@ def test_random_curves_match_oracle(ctx, oracle, seed, n, kw):
                             q_cap=prm.q_cap, depth_mode=prm.depth_mode, threads=THREADS)
     _compare(res, ref, periods, f"seed {seed}")
     sr, raw, sde, best = oracle.sde(ref.chi2, prm.median_window)
+    assert np.allclose(res.sde, sde, rtol=RTOL, atol=1e-12)
+    assert res.best_period == best
+
+
+@pytest.mark.parametrize("dt0,n_refine", [(0.1, 25), (0.3, 0), (0.05, 10 ** 6)])
+def test_two_stage_matches_oracle(ctx, oracle, dt0, n_refine):
+    """Coarse pass + every-offset refinement of the best-SDE periods."""
+    c = synth.curve_random(22, n=6000, inject=True)
+    span = c["t"].max() - c["t"].min()
+    periods = oracle.period_grid_ofir(span, 2.0, pmin_days=0.5, pmax_days=span / 2)
+    periods = periods[np.linspace(0, len(periods) - 1, 400).astype(int)]
+    durs = oracle.duration_grid(periods[0], periods[-1], 10)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 256)
+    _say("two-stage", dt0, n_refine)
+    prm = gtls.gtls_params_default(dt0=dt0)
+    res, refined = gtls.tls_search_refined(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, n_refine, prm)
+    ref, (sr, raw, sde, best), oref = oracle.tls_search_two_stage(c["t"], c["y"], c["dy"], periods, durs, tm,
+                                                                 dt0=dt0, n_refine=n_refine, threads=THREADS)
+    assert np.array_equal(refined, oref)
+    _compare(res, ref, periods, f"two-stage dt0={dt0} k={n_refine}")
     assert np.allclose(res.sde, sde, rtol=RTOL, atol=1e-12)
     assert res.best_period == best
 
