@@ -109,6 +109,7 @@ gtls_status gtls_create(gtls_ctx** out, int device, void* hip_stream) {
     if (e != hipSuccess) return fail(nullptr, GTLS_EDEVICE, hipGetErrorString(e));
     gtls_ctx* ctx = new gtls_ctx();
     ctx->device = device;
+    ctx->num_cus = prop.multiProcessorCount;     // sizes the persistent kernels
     if (hip_stream) {
         ctx->stream = (hipStream_t)hip_stream;
     } else {

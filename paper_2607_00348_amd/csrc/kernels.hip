@@ -1931,13 +1931,14 @@ template <typename T, bool VARW, bool MEAN>
 void launch_slides(const SlideArgs& la, unsigned grid, bool strided, int num_cus, hipStream_t s) {
     k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
     if (strided) {
+        // num_cus: compute units of the context's device, set at creation
         k_strided_plan<<<1, kPlanThreads, 0, s>>>(la);
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slide_strided<T, VARW, MEAN>, kSlideThreads, 0) !=
                 hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        k_slide_strided<T, VARW, MEAN><<<(unsigned)(per_cu * std::max(num_cus, 1)), kSlideThreads, 0, s>>>(la);
+        k_slide_strided<T, VARW, MEAN><<<(unsigned)(per_cu * num_cus), kSlideThreads, 0, s>>>(la);
     }
 }
 
@@ -2162,11 +2163,6 @@ hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& h) {
         anyvarw |= hm[(size_t)c * kMiscSlots + kWminBits] != hm[(size_t)c * kMiscSlots + kWmaxBits];
 
     // Persistent grid: workgroups per CU from the autotuner (per shape).
-    if (ctx->num_cus == 0) {
-        hipDeviceProp_t prop;
-        if ((e = hipGetDeviceProperties(&prop, ctx->device)) != hipSuccess) return e;
-        ctx->num_cus = prop.multiProcessorCount;
-    }
     const int max_per_cu = 2;
     const int64_t grid_max = (int64_t)ctx->num_cus * max_per_cu;
     const size_t scr = align256(2 * 8 * (size_t)n_max) + align256(es * (size_t)pstride) * (anyvarw ? 2 : 1) +
