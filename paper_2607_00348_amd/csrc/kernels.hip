@@ -649,7 +649,7 @@ struct SlideArgs {
     int32_t* toff;           // [bp nd + 1] first task of item (jrev bp + pl); last = total
     int32_t* tmap;           // [bp nd kTaskMax] item of task
     ItemBest* sb;            // [bp nd kTaskMax] best of task
-    uint32_t* queue;         // [2] next task, total
+    uint32_t* queue;         // [2 kXcds + 1] pop counters, queue starts, total
     int32_t rmax;            // most windows per lane (the FP32C rule keeps it at 4)
 };
 
@@ -902,20 +902,27 @@ __device__ Best slide_unit_tile(const SlideItem& si, int64_t i0, T* x_sh, T* xw_
 // takes it with template point j - r s.  The lane walks j upward over its
 // own contiguous run of the padded curve in chunks of 16 (the next chunk is
 // loaded while this one is used); window r skips the chunks outside
-// [r s, r s + D) and reads zeros from the table guards in the two partial
-// ones (x * 0 leaves the running sum unchanged exactly), so every window
-// still sums its D products in ascending template order.
+// [r s, r s + D) and reads zeros for template points outside [0, D) in the
+// two partial ones (x * 0 leaves the running sum unchanged exactly), so
+// every window still sums its D products in ascending template order.  The
+// template streams through a per-wave LDS ring: each chunk appends the next
+// 16 row points (fetched one chunk ahead), and window r reads its 16 from
+// the ring with in-order LDS loads.  The ring is written twice (at p and
+// p + kRing) so a 16-point read never wraps; it must hold the last
+// (R - 1) s + 32 points, which caps R.
 constexpr int kSC = 16;                             // j steps per chunk
 constexpr int kTaskMax = 16;                        // wave tasks per strided item
+constexpr int kRing = 1024;                         // template ring points per wave (stored twice)
 
 // Windows per lane: the largest of 8, 4, 2 (at most rmax) that still gives
 // `fill` lanes a window each, when consecutive windows overlap (s < D);
 // else 1.
 __host__ __device__ __forceinline__ int strided_r(int64_t nw, int64_t s, int64_t d, int64_t fill, int rmax) {
     if (s >= d) return 1;
-    if (rmax >= 8 && nw >= 8 * fill) return 8;
-    if (rmax >= 4 && nw >= 4 * fill) return 4;
-    if (nw >= 2 * fill) return 2;
+    auto fits = [&](int r) { return nw >= r * fill && (r - 1) * s + 2 * kSC <= kRing; };
+    if (rmax >= 8 && fits(8)) return 8;
+    if (rmax >= 4 && fits(4)) return 4;
+    if (fits(2)) return 2;
     return 1;
 }
 
@@ -954,13 +961,28 @@ __device__ __forceinline__ void run_chunk(T (&v)[kSC], const T* __restrict__ p, 
 
 template <typename T, bool VARW, int R>
 __device__ __forceinline__ void strided_chunk(double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
-                                              const T (&xw)[VARW ? kSC : 1], cptr<T> trow, int64_t c0, int64_t s,
+                                              const T (&xw)[VARW ? kSC : 1], const T* ring, int64_t c0, int64_t s,
                                               int64_t D) {
+    // window r + 1's template block is read while window r's products run
+    // (ring reads are always in range; inactive windows just skip the math)
+    T tn[kSC];
+    {
+        const T* tp = ring + (c0 & (kRing - 1));
+#pragma unroll
+        for (int u = 0; u < kSC; ++u) tn[u] = tp[u];
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t klo = c0 - (int64_t)r * s;     // template index of x[0] for window r
+        T t[kSC];
+#pragma unroll
+        for (int u = 0; u < kSC; ++u) t[u] = tn[u];
+        if (r + 1 < R) {
+            const T* tp = ring + ((klo - s) & (kRing - 1));
+#pragma unroll
+            for (int u = 0; u < kSC; ++u) tn[u] = tp[u];
+        }
         if (klo > -kSC && klo < D) {
-            const cptr<T> t = trow + klo;
             if constexpr (sizeof(T) == 8) {
 #pragma unroll
                 for (int u = 0; u < kSC; ++u) {
@@ -981,14 +1003,33 @@ __device__ __forceinline__ void strided_chunk(double (&acc)[R], double (&bacc)[V
     }
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Windows [m_lo, m_hi) of one item on one wave; returns the wave's first
-// best on every lane.  DB: load the next chunk while this one is used.
+// best on every lane.  ring: this wave's 2 kRing LDS points.  DB: load the
+// next chunk while this one is used.
 template <typename T, bool VARW, bool MEAN, int R, bool DB>
-__device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi) {
+__device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi, T* ring) {
     const int lane = threadIdx.x & 63;
     const int64_t s = si.stride, D = si.D;
-    const cptr<T> trow = (cptr<T>)si.trow;
+    const T* __restrict__ trow = (const T*)si.trow;
     const int64_t J = D + (R - 1) * s;              // j steps of a lane
+    // ring append: lanes 0..15 write template point c0 + lane (zero past D)
+    auto tfetch = [&](int64_t c0) -> T {
+        const int64_t k = c0 + lane;
+        return (lane < kSC && k < D) ? trow[k] : (T)0;
+    };
+    auto tput = [&](int64_t c0, T v) {
+        if (lane < kSC) {
+            const int p = (int)((c0 + lane) & (kRing - 1));
+            ring[p] = v;
+            ring[p + kRing] = v;
+        }
+    };
     Best best{-INFINITY, 0.0, -1};
     for (int64_t g0 = m_lo; g0 < m_hi; g0 += 64 * R) {
         const int64_t ml = g0 + (int64_t)lane * R;
@@ -1001,12 +1042,23 @@ __device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi)
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
 #pragma unroll
         for (int r = 0; r < (VARW ? R : 1); ++r) bacc[r] = 0.0;
+        // template points -16..-1 read as zero until the ring wraps past them
+        wave_sync();
+        if (lane < kSC) {
+            ring[kRing - kSC + lane] = (T)0;
+            ring[2 * kRing - kSC + lane] = (T)0;
+        }
+        T tcur = tfetch(0);
         if constexpr (!DB) {
             T va[kSC], wa[VARW ? kSC : 1];
             for (int64_t c0 = 0; c0 < J; c0 += kSC) {
                 run_chunk(va, xp, c0, avail);
                 if constexpr (VARW) run_chunk(wa, xq, c0, avail);
-                strided_chunk<T, VARW, R>(acc, bacc, va, wa, trow, c0, s, D);
+                tput(c0, tcur);
+                wave_sync();
+                tcur = tfetch(c0 + kSC);
+                strided_chunk<T, VARW, R>(acc, bacc, va, wa, ring, c0, s, D);
+                wave_sync();
             }
         } else {
             T va[kSC], vb[kSC], wa[VARW ? kSC : 1], wb[VARW ? kSC : 1];
@@ -1018,13 +1070,21 @@ __device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi)
                     run_chunk(vb, xp, c0 + kSC, avail);
                     if constexpr (VARW) run_chunk(wb, xq, c0 + kSC, avail);
                 }
-                strided_chunk<T, VARW, R>(acc, bacc, va, wa, trow, c0, s, D);
+                tput(c0, tcur);
+                wave_sync();
+                tcur = tfetch(c0 + kSC);
+                strided_chunk<T, VARW, R>(acc, bacc, va, wa, ring, c0, s, D);
+                wave_sync();
                 if (!more) break;
                 if (c0 + 2 * kSC < J) {
                     run_chunk(va, xp, c0 + 2 * kSC, avail);
                     if constexpr (VARW) run_chunk(wa, xq, c0 + 2 * kSC, avail);
                 }
-                strided_chunk<T, VARW, R>(acc, bacc, vb, wb, trow, c0 + kSC, s, D);
+                tput(c0 + kSC, tcur);
+                wave_sync();
+                tcur = tfetch(c0 + 2 * kSC);
+                strided_chunk<T, VARW, R>(acc, bacc, vb, wb, ring, c0 + kSC, s, D);
+                wave_sync();
             }
         }
 #pragma unroll
@@ -1043,14 +1103,14 @@ __device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi)
 }
 
 template <typename T, bool VARW, bool MEAN, int RMAX, bool DB>
-__device__ Best strided_windows_r(int R, const SlideItem& si, int64_t m_lo, int64_t m_hi) {
+__device__ Best strided_windows_r(int R, const SlideItem& si, int64_t m_lo, int64_t m_hi, T* ring) {
     switch (R) {
         case 8:
-            if constexpr (RMAX >= 8) return strided_windows<T, VARW, MEAN, 8, DB>(si, m_lo, m_hi);
+            if constexpr (RMAX >= 8) return strided_windows<T, VARW, MEAN, 8, DB>(si, m_lo, m_hi, ring);
             [[fallthrough]];
-        case 4: return strided_windows<T, VARW, MEAN, 4, DB>(si, m_lo, m_hi);
-        case 2: return strided_windows<T, VARW, MEAN, 2, DB>(si, m_lo, m_hi);
-        default: return strided_windows<T, VARW, MEAN, 1, DB>(si, m_lo, m_hi);
+        case 4: return strided_windows<T, VARW, MEAN, 4, DB>(si, m_lo, m_hi, ring);
+        case 2: return strided_windows<T, VARW, MEAN, 2, DB>(si, m_lo, m_hi, ring);
+        default: return strided_windows<T, VARW, MEAN, 1, DB>(si, m_lo, m_hi, ring);
     }
 }
 
@@ -1119,10 +1179,38 @@ __global__ __launch_bounds__(kSlideThreads) void k_slide_unit(SlideArgs a) {
 }
 
 constexpr int kPlanThreads = 1024;
+constexpr int kXcds = 8;                 // MI355X: workgroups go round-robin over 8 XCDs (L2 domains)
 
-// Lists the wave tasks of the strided items of one launch in launch order
-// (longest duration first): toff[idx] is the first task of item idx = jrev
-// bp + pl, toff[bp nd] the total; tmap[task] = idx.  Resets the task queue.
+// Strided items in queue order: periods are dealt to kXcds queues (pl mod
+// kXcds), each queue lists its periods in order, and each period its
+// durations longest first, so the waves of one XCD work on a few periods at
+// a time and their padded curves stay in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_periods(int bp, int x) { return (bp - x + kXcds - 1) / kXcds; }
+
+__device__ __forceinline__ int64_t queue_index(int bp, int nd, int pl, int j) {
+    const int x = pl % kXcds;
+    int64_t off = 0;
+    for (int y = 0; y < x; ++y) off += xcd_periods(bp, y);
+    return (off + pl / kXcds) * nd + (nd - 1 - j);
+}
+
+__device__ __forceinline__ void queue_item(int bp, int nd, int64_t idx, int& pl, int& j) {
+    int64_t q = idx / nd;
+    const int jrev = (int)(idx - q * nd);
+    int x = 0;
+    for (; x < kXcds - 1; ++x) {
+        const int64_t c = xcd_periods(bp, x);
+        if (q < c) break;
+        q -= c;
+    }
+    pl = (int)(q * kXcds + x);
+    j = nd - 1 - jrev;
+}
+
+// Lists the wave tasks of the strided items of one launch in queue order:
+// toff[idx] is the first task of item idx, toff[bp nd] the total, tmap[task]
+// = idx; queue[kXcds + x] is the first task of XCD queue x (queue[2 kXcds]
+// the total) and queue[x] its pop counter, reset here.
 __global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
     __shared__ int32_t part[kPlanThreads];
     const int tid = threadIdx.x;
@@ -1130,9 +1218,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
     const int64_t per = (items + kPlanThreads - 1) / kPlanThreads;
     const int64_t lo = min(items, (int64_t)tid * per), hi = min(items, lo + per);
     auto count = [&](int64_t idx) -> int {
-        const int jrev = (int)(idx / a.bp);
-        const int pl = (int)(idx - (int64_t)jrev * a.bp);
-        const double period = a.periods[pl], dur = a.durations[a.nd - 1 - jrev];
+        int pl, j;
+        queue_item(a.bp, a.nd, idx, pl, j);
+        const double period = a.periods[pl], dur = a.durations[j];
         if (!duration_valid(period, dur, a.prm)) return 0;
         const int64_t d = points_in(a.n, period, dur);
         const int64_t st = t0_stride(d, a.prm.dt0);
@@ -1155,51 +1243,65 @@ __global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
         for (int t = 0; t < c; ++t) a.tmap[o + t] = (int32_t)idx;
         o += c;
     }
-    if (tid == kPlanThreads - 1) {
-        a.toff[items] = part[tid];
-        a.queue[0] = 0u;
-        a.queue[1] = (uint32_t)part[tid];
+    if (tid == 0) a.toff[items] = part[kPlanThreads - 1];
+    __syncthreads();
+    if (tid < kXcds) {
+        int64_t first = 0;
+        for (int y = 0; y < tid; ++y) first += xcd_periods(a.bp, y);
+        a.queue[tid] = 0u;
+        a.queue[kXcds + tid] = (uint32_t)a.toff[first * a.nd];
     }
+    if (tid == kXcds) a.queue[2 * kXcds] = (uint32_t)part[kPlanThreads - 1];
 }
 
-// Persistent: every wave pops wave tasks until the list is exhausted.
+// Persistent: every wave pops wave tasks from its XCD's queue, then from the
+// others, until all are exhausted.
 template <typename T, bool VARW, bool MEAN>
 __global__ __launch_bounds__(kSlideThreads) void k_slide_strided(SlideArgs a) {
+    __shared__ T rings[(kSlideThreads / 64) * 2 * kRing];
     const int lane = threadIdx.x & 63;
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.queue[1]);
-    for (;;) {
-        // Every lane takes part in the pop (lane 0 adds 1, the rest 0) so no
-        // divergent branch feeds the broadcast of lane 0's ticket.
-        const uint32_t ticket = atomicAdd(&a.queue[0], lane == 0 ? 1u : 0u);
-        const uint32_t task = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
-        if (task >= total) break;
-        const int32_t idx = __builtin_amdgcn_readfirstlane(a.tmap[task]);
-        const int t = (int)task - __builtin_amdgcn_readfirstlane(a.toff[idx]);
-        ItemInfo it;
-        const int jrev = idx / a.bp;
-        it.pl = idx - jrev * a.bp;
-        it.j = a.nd - 1 - jrev;
-        it.tile = 0;
-        it.valid = true;
-        it.period = a.periods[it.pl];
-        it.d = points_in(a.n, it.period, a.durations[it.j]);
-        it.stride = t0_stride(it.d, a.prm.dt0);
-        const SlideItem si = make_item<T, MEAN>(a, it, VARW);
-        const StridedSplit sp = strided_split(a.n, it.d, it.stride, 64, kTaskMax, a.rmax);
-        int64_t m_lo, m_hi;
-        strided_task_range(sp, t, m_lo, m_hi);
-        const Best b = strided_windows_r<T, VARW, MEAN, 8, true>(sp.R, si, m_lo, m_hi);
-        if (lane == 0) {
-            ItemBest* o = a.sb + task;
-            o->dchi2 = b.dchi2;
-            o->depth = b.depth;
-            o->start = (int32_t)b.start;
-            o->d = (int32_t)it.d;
-            o->evals = (int32_t)(m_hi - m_lo);
-            o->ntiles = 0;
+    T* ring = rings + (threadIdx.x >> 6) * 2 * kRing;
+    const int x0 = (int)(blockIdx.x % kXcds);
+    for (int k = 0; k < kXcds; ++k) {
+        const int x = (x0 + k) % kXcds;
+        const uint32_t qb = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.queue[kXcds + x]);
+        const uint32_t qe = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.queue[kXcds + x + 1]);
+        for (;;) {
+            // Every lane takes part in the pop (lane 0 adds 1, the rest 0) so
+            // no divergent branch feeds the broadcast of lane 0's ticket.
+            const uint32_t ticket = atomicAdd(&a.queue[x], lane == 0 ? 1u : 0u);
+            const uint32_t task = qb + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
+            if (task >= qe) break;
+            const int32_t idx = __builtin_amdgcn_readfirstlane(a.tmap[task]);
+            const int t = (int)task - __builtin_amdgcn_readfirstlane(a.toff[idx]);
+            ItemInfo it;
+            int pl, j;
+            queue_item(a.bp, a.nd, idx, pl, j);
+            it.pl = pl;
+            it.j = j;
+            it.tile = 0;
+            it.valid = true;
+            it.period = a.periods[it.pl];
+            it.d = points_in(a.n, it.period, a.durations[it.j]);
+            it.stride = t0_stride(it.d, a.prm.dt0);
+            const SlideItem si = make_item<T, MEAN>(a, it, VARW);
+            const StridedSplit sp = strided_split(a.n, it.d, it.stride, 64, kTaskMax, a.rmax);
+            int64_t m_lo, m_hi;
+            strided_task_range(sp, t, m_lo, m_hi);
+            const Best b = strided_windows_r<T, VARW, MEAN, 8, true>(sp.R, si, m_lo, m_hi, ring);
+            if (lane == 0) {
+                ItemBest* o = a.sb + task;
+                o->dchi2 = b.dchi2;
+                o->depth = b.depth;
+                o->start = (int32_t)b.start;
+                o->d = (int32_t)it.d;
+                o->evals = (int32_t)(m_hi - m_lo);
+                o->ntiles = 0;
+            }
         }
     }
 }
+
 // ------------------------------------------------------------------------
 // Per-period reduction over durations and the T0 of the best window.
 
@@ -1232,7 +1334,7 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
         double best = -INFINITY, bdepth = 0.0;
         int bj = -1, bi = -1, bd = 0;
         for (int j = 0; j < a.nd; ++j) {
-            const int64_t idx = (int64_t)(a.nd - 1 - j) * a.bp + pl;
+            const int64_t idx = queue_index(a.bp, a.nd, pl, j);
             const ItemBest* slots = a.items + ((size_t)pl * a.nd + j) * a.ntiles;
             int nt;
             if (a.toff && a.toff[idx + 1] > a.toff[idx]) {
@@ -1749,8 +1851,9 @@ __global__ __launch_bounds__(kBatchThreads, 2) void k_batch(BatchArgs a) {
                 int64_t m_lo = 0, m_hi = 0;
                 if (wave < sp.ntask) strided_task_range(sp, wave, m_lo, m_hi);
                 Best lb;
-                if (ANYVARW && varw) lb = strided_windows_r<T, ANYVARW, MEAN, 4, false>(sp.R, si, m_lo, m_hi);
-                else lb = strided_windows_r<T, false, MEAN, 4, false>(sp.R, si, m_lo, m_hi);
+                T* ring = reinterpret_cast<T*>(dyn) + wave * 2 * kRing;
+                if (ANYVARW && varw) lb = strided_windows_r<T, ANYVARW, MEAN, 4, false>(sp.R, si, m_lo, m_hi, ring);
+                else lb = strided_windows_r<T, false, MEAN, 4, false>(sp.R, si, m_lo, m_hi, ring);
                 jb = block_best(lb, bs.red);
             }
             if (jb.dchi2 > pbest.dchi2) {
@@ -1920,7 +2023,7 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     p.off_sb = o;
     o = align256(o + sizeof(ItemBest) * (size_t)nd * kTaskMax * bp);
     p.off_queue = o;
-    o = align256(o + 2 * sizeof(uint32_t));
+    o = align256(o + (2 * kXcds + 1) * sizeof(uint32_t));
     p.per_batch = o;
     return p;
 }
@@ -2051,7 +2154,8 @@ size_t batch_lds_bytes() {
     const size_t es = sizeof(T), mult = ANYVARW ? 2 : 1;
     const size_t sort = sizeof(SortShared<kBatchThreads>);
     const size_t unit = (size_t)xpad<T>(kXs) * es * mult;
-    return std::max(sort, unit);
+    const size_t ring = (size_t)(kBatchThreads / 64) * 2 * kRing * es;
+    return std::max(sort, std::max(unit, ring));
 }
 
 template <typename T, bool MEAN, bool ANYVARW>
