@@ -140,19 +140,55 @@ def sort_bytes(n: int, periods, durs, prm) -> float:
     per element-period 8 B of t, three radix passes over the packed 8-byte
     (key, index) word (the first computes it: 8 B written; the others read
     and write it: 32 B), and the padded residuals, 8 B (4 B in FP32C) per
-    position over n + D_max(P) positions, plus the weights when dy varies
-    (not in these workloads) and the 16 B (8 B) prefix sums in MEAN mode."""
-    p = np.asarray(periods)[:, None]
-    q = np.asarray(durs)[None, :] / p
-    ps = p * 86400.0
-    ok = (q <= prm.q_cap)
-    if prm.envelope:
-        ok &= (q ** 3 * ps ** 2 >= prm.k_min ** 3) & (q ** 3 * ps ** 2 <= prm.k_max ** 3)
-    d = np.clip(np.floor(n * q + 0.5), 1, n)
-    dmax = np.where(ok, d, 0).max(axis=1)
+    position over n + D_max(P) positions, plus the 16 B (8 B) prefix sums in
+    MEAN mode (per-point weights, absent from these workloads, would add as
+    much again as the residuals)."""
+    dmax = _valid_d(n, periods, durs, prm).max(axis=1)
     es = 4.0 if prm.precision == 1 else 8.0
     per_pos = es + ((8.0 if prm.precision == 1 else 16.0) if prm.depth_mode == 1 else 0.0)
     return float(np.sum(8.0 * n + 8.0 * n + 32.0 * n + per_pos * (n + dmax)))
+
+
+def _valid_d(n: int, periods, durs, prm):
+    """Points per window D for every (period, duration), 0 where the
+    duration is outside the period's envelope."""
+    p = np.asarray(periods)[:, None]
+    q = np.asarray(durs)[None, :] / p
+    ps = p * 86400.0
+    ok = q <= prm.q_cap
+    if prm.envelope:
+        ok &= (q ** 3 * ps ** 2 >= prm.k_min ** 3) & (q ** 3 * ps ** 2 <= prm.k_max ** 3)
+    d = np.clip(np.floor(n * q + 0.5), 1, n)
+    return np.where(ok, d, 0).astype(np.int64)
+
+
+def strided_mac_count(n: int, periods, durs, prm) -> float:
+    """Multiply-adds of the strided items (T0 stride >= 2): windows x D."""
+    d = _valid_d(n, periods, durs, prm)
+    s = np.maximum(1, np.floor(prm.dt0 * d)).astype(np.int64)
+    use = (d > 0) & (s >= 2)
+    nw = (n + s - 1) // np.maximum(s, 1)
+    return float(np.sum(np.where(use, nw * d, 0)))
+
+
+def measured_traffic(kernel: str, args):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    factor a plain copy of known size gives), or None when there is none or
+    the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"traffic_{args.workload}_dt0_{args.dt0:g}_{args.precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2607_00348_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    k = rec["kernels"].get(kernel)
+    if not k:
+        return None
+    return k["fetch_kib_per_launch"] * 1024 * rec["fetch_factor"] + k["write_kib_per_launch"] * 1024 * rec["write_factor"]
 
 
 def copy_probe(nbytes: int):
@@ -180,7 +216,7 @@ def main():
     ap.add_argument("--dt0", type=float, default=0.1)
     ap.add_argument("--depth-mode", choices=["wls", "mean"], default="wls")
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
-    ap.add_argument("--cpu-sample", type=int, default=1024, help="periods the oracle baseline runs on")
+    ap.add_argument("--cpu-sample", type=int, default=12000, help="periods the oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of this many bytes (counter calibration)")
@@ -250,22 +286,26 @@ def main():
         print(f"[bench] stage {k:10s} {ms / args.steps:10.3f} ms/step  {nl // args.steps} launches/step",
               file=sys.stderr, flush=True)
 
-    # Roofline of the stage with the largest share of kernel time.
+    # Roofline of the kernel stage with the largest share of kernel time.
     stage = max(prof, key=lambda k: prof[k][0])
     stage_ms = prof[stage][0] / args.steps
     launches = max(1, prof[stage][1] // args.steps)
-    if stage == "slide":
-        flops = 2.0 * float(n_macs)                        # one multiply-add per template point per window
-        achieved = flops / (stage_ms * 1e-3) / 1e12
+    per_launch_ms = stage_ms / launches
+    strided_macs = strided_mac_count(len(c["t"]), periods, durs, prm)
+    if stage in ("slide", "slide_strided"):
+        macs = strided_macs if stage == "slide_strided" else float(n_macs) - strided_macs
+        flops = 2.0 * macs / launches                     # one multiply-add per template point per window
+        achieved = flops / (per_launch_ms * 1e-3) / 1e12
+        kernel = "k_slide_strided" if stage == "slide_strided" else "k_slide_unit"
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "k_slide",
-                "per_launch_ms": stage_ms / launches}
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kernel, args),
+                "kernel": kernel, "per_launch_ms": per_launch_ms, "flops_per_launch": flops}
     else:
-        byts = sort_bytes(len(c["t"]), periods, durs, prm)
-        achieved = byts / (stage_ms * 1e-3) / 1e9
+        byts = sort_bytes(len(c["t"]), periods, durs, prm) / launches
+        achieved = byts / (per_launch_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_fold_sort",
-                "per_launch_ms": stage_ms / launches}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic("k_fold_sort", args),
+                "kernel": "k_fold_sort", "per_launch_ms": per_launch_ms, "bytes_per_launch": byts}
 
     line = {"metric": METRIC, "value": evals_per_s, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",

@@ -127,7 +127,7 @@ hipError_t ensure(gtls_ctx* ctx, DeviceBuffer& b, size_t bytes);
 hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& a);
 hipError_t profile_collect(gtls_ctx* ctx);
 
-enum Stage { kStagePrep = 0, kStageSort = 1, kStageSlide = 2, kStageReduce = 3, kStageSde = 4 };
+enum Stage { kStagePrep = 0, kStageSort = 1, kStageSlide = 2, kStageReduce = 3, kStageSde = 4, kStageStrided = 5 };
 
 // Brackets one kernel launch with events on the context's stream when
 // profiling is on.

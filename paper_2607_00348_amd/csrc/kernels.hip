@@ -238,7 +238,13 @@ struct SortShared {
     uint32_t hist[3][256];
     uint32_t wcnt[NT / 64][256];
     uint32_t dbase[256];
-    __int128 part[NT];
+    uint32_t tcount[256];        // this tile's count per digit
+    uint32_t tstart[256];        // ... and its first slot in the tile's digit order
+    uint32_t wtot[4];
+    union {
+        uint64_t buf[NT * kSortItems];   // a tile in digit order (sort passes)
+        __int128 part[NT];               // per-thread partial sums (prefix sums)
+    };
     int64_t dpad;
 };
 
@@ -383,26 +389,51 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
                 if (tile0 + TILE < n) fetch(tile0 + TILE, nxt);
             }
             __syncthreads();
+            // per digit: the waves' exclusive offsets within the tile, and the tile's count
             if (tid < 256) {
-                uint32_t run = sh.dbase[tid];
+                uint32_t run = 0;
                 for (int w2 = 0; w2 < W; ++w2) {
                     const uint32_t c = sh.wcnt[w2][tid];
                     sh.wcnt[w2][tid] = run;
                     run += c;
                 }
-                sh.dbase[tid] = run;
+                sh.tcount[tid] = run;
+                // inclusive scan of the counts over the 256 digits: per wave, then across waves
+                uint32_t v = run;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t o = __shfl_up(v, off);
+                    if (lane >= off) v += o;
+                }
+                if (lane == 63) sh.wtot[tid >> 6] = v;
+                sh.tstart[tid] = v - run;
             }
             __syncthreads();
+            if (tid >= 64 && tid < 256) {
+                uint32_t add = 0;
+                for (int w2 = 0; w2 < (tid >> 6); ++w2) add += sh.wtot[w2];
+                sh.tstart[tid] += add;
+            }
+            __syncthreads();
+            // the tile in digit order (stable: waves, then items, then lanes, follow input order) ...
 #pragma unroll
             for (int e = 0; e < kSortItems; ++e) {
                 const int64_t idx = seg0 + e * 64 + lane;
-                const uint32_t pos = sh.wcnt[wave][dig[e]] + rnk[e];
-                if (idx < n && pos < (uint32_t)n) {
-                    dst[pos] = item[e];
-                    if (pass == 2 && gather) pad_store(po, n, pos, (uint32_t)item[e]);
+                if (idx < n) sh.buf[sh.tstart[dig[e]] + sh.wcnt[wave][dig[e]] + rnk[e]] = item[e];
+            }
+            __syncthreads();
+            // ... written out by consecutive threads: each digit's run lands contiguously
+            const int tn = (int)min((int64_t)TILE, n - tile0);
+            for (int i = tid; i < tn; i += NT) {
+                const uint64_t it = sh.buf[i];
+                const uint32_t d = (uint32_t)(it >> shift) & 255u;
+                const uint32_t pos = sh.dbase[d] + (uint32_t)i - sh.tstart[d];
+                if (pos < (uint32_t)n) {
+                    dst[pos] = it;
+                    if (pass == 2 && gather) pad_store(po, n, pos, (uint32_t)it);
                 }
             }
             __syncthreads();
+            if (tid < 256) sh.dbase[tid] += sh.tcount[tid];
             for (int k = tid; k < W * 256; k += NT) (&sh.wcnt[0][0])[k] = 0;
             __syncthreads();
             if constexpr (PREFETCH) {
@@ -2031,9 +2062,13 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
 // Unit-stride tiles, then (strided T0 grids) the wave-task list and the
 // persistent strided kernel, sized to fill every CU.
 template <typename T, bool VARW, bool MEAN>
-void launch_slides(const SlideArgs& la, unsigned grid, bool strided, int num_cus, hipStream_t s) {
-    k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
+void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strided, int num_cus, hipStream_t s) {
+    {
+        StageTimer tm(ctx, kStageSlide);
+        k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
+    }
     if (strided) {
+        StageTimer tm(ctx, kStageStrided);
         // num_cus: compute units of the context's device, set at creation
         k_strided_plan<<<1, kPlanThreads, 0, s>>>(la);
         int per_cu = 0;
@@ -2046,14 +2081,14 @@ void launch_slides(const SlideArgs& la, unsigned grid, bool strided, int num_cus
 }
 
 template <typename T>
-void launch_slides(const SlideArgs& la, unsigned grid, bool strided, bool varw, bool mean, int num_cus,
-                   hipStream_t s) {
+void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strided, bool varw, bool mean,
+                   int num_cus, hipStream_t s) {
     if (varw) {
-        if (mean) launch_slides<T, true, true>(la, grid, strided, num_cus, s);
-        else launch_slides<T, true, false>(la, grid, strided, num_cus, s);
+        if (mean) launch_slides<T, true, true>(ctx, la, grid, strided, num_cus, s);
+        else launch_slides<T, true, false>(ctx, la, grid, strided, num_cus, s);
     } else {
-        if (mean) launch_slides<T, false, true>(la, grid, strided, num_cus, s);
-        else launch_slides<T, false, false>(la, grid, strided, num_cus, s);
+        if (mean) launch_slides<T, false, true>(ctx, la, grid, strided, num_cus, s);
+        else launch_slides<T, false, false>(ctx, la, grid, strided, num_cus, s);
     }
 }
 
@@ -2126,11 +2161,8 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
         SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.prm, rpad, wpad, pfx, pl.pstride,
                      misc, table, bsum, s1sum, items, pl.ntiles, toff, tmap, sb, queue, pl.f32 ? 4 : 8};
         const unsigned grid = (unsigned)bp * (unsigned)a.n_durations * (unsigned)pl.ntiles;
-        {
-            StageTimer tm(ctx, kStageSlide);
-            if (pl.f32) launch_slides<float>(la, grid, strided, varw, pl.mean, ctx->num_cus, s);
-            else launch_slides<double>(la, grid, strided, varw, pl.mean, ctx->num_cus, s);
-        }
+        if (pl.f32) launch_slides<float>(ctx, la, grid, strided, varw, pl.mean, ctx->num_cus, s);
+        else launch_slides<double>(ctx, la, grid, strided, varw, pl.mean, ctx->num_cus, s);
         ReduceArgs ra{a.t, n, a.periods + p0, bp, a.n_durations, items, pl.ntiles, strided ? toff : nullptr, sb,
                       keys_a, misc, misc,
                       a.chi2 + p0, a.best_dur + p0, a.best_start + p0, a.depth + p0, a.t0 + p0};

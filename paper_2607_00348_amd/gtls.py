@@ -53,7 +53,7 @@ class gtls_summary(ctypes.Structure):
                 ("n_macs", ctypes.c_int64), ("best_period", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
-STAGES = ("prep", "fold_sort", "slide", "reduce", "sde")
+STAGES = ("prep", "fold_sort", "slide", "reduce", "sde", "slide_strided")
 
 
 class gtls_profile(ctypes.Structure):
