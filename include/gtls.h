@@ -109,9 +109,9 @@ typedef struct {
 
 /* Per-stage kernel timing, accumulated while profiling is on.  Stages:
  * 0 per-point preparation and chi2_0, 1 fold + sort + padding, 2 template
- * slide on every T0 offset (stride 1), 3 per-period reduction,
- * 4 periodogram statistics, 5 template slide on strided T0 grids (its task
- * planning and the persistent kernel). */
+ * slide on every T0 offset (stride 1) and the task list of strided T0
+ * grids, 3 per-period reduction, 4 periodogram statistics, 5 template slide
+ * on strided T0 grids. */
 #define GTLS_N_STAGES 6
 typedef struct {
     double ms[8];          /* summed kernel time per stage (HIP events on the

@@ -2066,11 +2066,11 @@ void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strid
     {
         StageTimer tm(ctx, kStageSlide);
         k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
+        if (strided) k_strided_plan<<<1, kPlanThreads, 0, s>>>(la);
     }
     if (strided) {
         StageTimer tm(ctx, kStageStrided);
         // num_cus: compute units of the context's device, set at creation
-        k_strided_plan<<<1, kPlanThreads, 0, s>>>(la);
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slide_strided<T, VARW, MEAN>, kSlideThreads, 0) !=
                 hipSuccess ||
