@@ -68,11 +68,13 @@ def search_inputs():
     return grid, durs, tm
 
 
-def batched_search(ctx, curves, grids, durs, tm, params=None, chunk=512):
+def batched_search(ctx, curves, grids, durs, tm, params=None, chunk=512, log=None):
     """Full search of many curves (each its own grid) through the batched
     path, in chunks; returns per-curve (best period, SDE max, chi2 array)."""
     best, sde, chi2 = [], [], []
     for c0 in range(0, len(curves), chunk):
+        if log and c0 and c0 % (8 * chunk) == 0:
+            log(f"searched {c0} of {len(curves)} curves")
         cs = curves[c0:c0 + chunk]
         gs = grids[c0:c0 + chunk]
         off = np.cumsum([0] + [len(c["t"]) for c in cs])
@@ -111,21 +113,25 @@ def recall_at_k(ranked_bins: np.ndarray, labels: np.ndarray) -> float:
 
 
 def run(n_train: int, n_test: int, steps: int, k: int = 32, seed: int = 0, accept: float = 7.0,
-        log=print) -> dict:
+        lr: float = 1e-3, batch: int = 64, log=print) -> dict:
     ctx = gtls.Context(0)
     grid, durs, tm = search_inputs()
     log(f"grid {len(grid)} periods, {len(durs)} durations")
     t0 = time.perf_counter()
-    train_c = [training_curve(i, seed) for i in range(n_train)]
+    train_c = []
+    for i in range(n_train):
+        train_c.append(training_curve(i, seed))
+        if (i + 1) % 8192 == 0:
+            log(f"generated {i + 1} training curves")
     test_c = [training_curve(10_000_000 + i, seed) for i in range(n_test)]
     log(f"curves generated in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    tr_best, tr_sde, _ = batched_search(ctx, train_c, [grid] * n_train, durs, tm)
+    tr_best, tr_sde, _ = batched_search(ctx, train_c, [grid] * n_train, durs, tm, log=log)
     log(f"training labels (full-grid searches) in {time.perf_counter() - t0:.1f} s")
     tr_lab = period_bin(tr_best)
     v_tr = views_of(ctx, train_c)
     t0 = time.perf_counter()
-    net, losses = train(ctx, v_tr, tr_lab, steps, seed=seed, log=log)
+    net, losses = train(ctx, v_tr, tr_lab, steps, batch=batch, lr=lr, seed=seed, log=log)
     t_train = time.perf_counter() - t0
     log(f"trained {steps} steps in {t_train:.1f} s")
 
@@ -155,7 +161,8 @@ def run(n_train: int, n_test: int, steps: int, k: int = 32, seed: int = 0, accep
     prior = np.argsort(-np.bincount(tr_lab, minlength=N_BINS), kind="stable")[:k]
     strong = te_sde >= 7.0
     out = {
-        "n_train": n_train, "n_test": n_test, "steps": steps, "k": k, "grid_periods": int(len(grid)),
+        "n_train": n_train, "n_test": n_test, "steps": steps, "batch": batch, "lr": lr, "k": k,
+        "grid_periods": int(len(grid)),
         "final_loss": float(np.mean(losses[-50:])), "train_seconds": t_train,
         "recall_at_k_net": recall_at_k(top, te_lab),
         "recall_at_k_net_sde7": recall_at_k(top[strong], te_lab[strong]) if strong.any() else None,
@@ -184,9 +191,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--accept", type=float, default=7.0, help="pruned SDE below this falls back to the full grid")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    res = run(a.train, a.test, a.steps, a.k, accept=a.accept, log=lambda m: print(f"[learned] {m}", file=sys.stderr, flush=True))
+    res = run(a.train, a.test, a.steps, a.k, accept=a.accept, lr=a.lr, batch=a.batch, log=lambda m: print(f"[learned] {m}", file=sys.stderr, flush=True))
     s = json.dumps(res)
     print(s, flush=True)
     if a.out:
