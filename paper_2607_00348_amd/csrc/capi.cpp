@@ -42,7 +42,8 @@ gtls_status check_params(gtls_ctx* ctx, const gtls_params& p) {
 }
 
 gtls_status check_sizes(gtls_ctx* ctx, int64_t n, int32_t np, int32_t nd, int32_t nt) {
-    if (n < 3 || n > 0x7fffffff) return fail(ctx, GTLS_EINVAL, "n must be in [3, 2^31)");
+    // the strided slide addresses a padded curve (at most 2 n + 1088 points) with 32-bit byte offsets
+    if (n < 3 || n > (1 << 27)) return fail(ctx, GTLS_EINVAL, "n must be in [3, 2^27]");
     if (np < 1) return fail(ctx, GTLS_EINVAL, "n_periods must be >= 1");
     if (nd < 1) return fail(ctx, GTLS_EINVAL, "n_durations must be >= 1");
     if (nt < 2) return fail(ctx, GTLS_EINVAL, "n_tmpl must be >= 2");

@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <utility>
 
 #include "gtls_impl.hpp"
 
@@ -258,6 +259,11 @@ __device__ __forceinline__ uint32_t phase_key(double ph) {
     const double x = ph * kTwo24;
     return x >= kTwo24 ? kKeyMax : (uint32_t)x;
 }
+
+// Zeros kept after every padded curve of the single-curve search: the
+// strided slide reads 16-byte pieces that start at most at the end of the
+// padded curve.
+constexpr int64_t kOverRead = 16;
 
 // Where the sorted order goes: the padded residual / weight copies (npad
 // positions, position k holding sorted point k mod n), or nothing (rpad
@@ -586,6 +592,17 @@ __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
     fold_sort_core<kSortThreads, true>(a.t, n, period, A, B, po, sh);
     pad_prefix<kSortThreads>(A, n, npad, a.u, a.pfx ? (char*)a.pfx + (size_t)pl * (a.pstride + 1) * ps : nullptr,
                              a.f32 != 0, sh);
+    if (po.rpad) {
+        for (int64_t k = npad + threadIdx.x; k < npad + kOverRead; k += kSortThreads) {
+            if (a.f32) {
+                ((float*)po.rpad)[k] = 0.0f;
+                if (po.wpad) ((float*)po.wpad)[k] = 0.0f;
+            } else {
+                ((double*)po.rpad)[k] = 0.0;
+                if (po.wpad) ((double*)po.wpad)[k] = 0.0;
+            }
+        }
+    }
     if (a.perm_out) {
         int32_t* po = a.perm_out + (size_t)pl * n;
         for (int64_t k = threadIdx.x; k < n; k += kSortThreads) po[k] = (int32_t)(uint32_t)A[k];
@@ -682,6 +699,7 @@ struct SlideArgs {
     ItemBest* sb;            // [bp nd kTaskMax] best of task
     uint32_t* queue;         // [2 kXcds + 1] pop counters, queue starts, total
     int32_t rmax;            // most windows per lane (the FP32C rule keeps it at 4)
+    int32_t rcost;           // 1: windows per lane by the wave-chunk count (FP64), 0: the FP32C rule
 };
 
 struct Best {
@@ -1145,6 +1163,292 @@ __device__ Best strided_windows_r(int R, const SlideItem& si, int64_t m_lo, int6
     }
 }
 
+// Strided windows with coalesced curve loads (the persistent single-curve
+// kernel).  Same windows, chunks and per-window sums as strided_windows, with
+// two changes to where the operands come from:
+//  - each 16-point chunk of the 64 lanes' runs is loaded cooperatively: 8
+//    lanes (FP64) or 4 lanes (FP32) read one lane's chunk as 16-byte pieces,
+//    so one load instruction touches 8 or 16 runs instead of 64; the pieces
+//    go to a per-wave LDS buffer of 64 padded rows and every lane reads its
+//    own row back;
+//  - the template block of window r (16 points from c0 - r s) is loaded from
+//    the table with lane l holding point l mod 16, and each multiply-add takes
+//    its template point by a DPP row broadcast from lane u of the 16-lane row,
+//    so no template value passes through LDS.
+// The next chunk's loads are issued before this chunk's products.  Windows
+// outside their span in a chunk multiply by template zeros (the row guards,
+// or an explicit zero when the block lies wholly outside the row), which
+// leaves their sums unchanged exactly.
+template <typename T>
+constexpr int kPiece = 16 / (int)sizeof(T);                  // points per 16-byte piece
+template <typename T>
+constexpr int kStRow = kSC + kPiece<T>;                      // staging row stride (points), 16-byte pad
+template <typename T>
+constexpr int kStage = 64 * kStRow<T>;                       // staging points per wave and array
+
+template <typename T>
+struct Piece {
+    T v[kPiece<T>];
+};
+
+template <typename T>
+__device__ __forceinline__ Piece<T> load_piece(const T* p) {
+    Piece<T> r;
+    __builtin_memcpy(&r, p, 16);
+    return r;
+}
+
+// acc[r] = fma(t, x, acc[r]) for every window r, with t the value of tv[r]
+// in lane (l & ~15) + U of the lane's 16-lane row (a DPP row broadcast).  One
+// fused multiply-add instruction per window, so the broadcast values are never
+// materialised in registers.  The leading s_nop 1 gives the two wait states a
+// DPP read needs after a vector ALU write of any of its registers; inside the
+// block every instruction writes a different accumulator, so the next block's
+// read of an accumulator is at least two wait states after its write as well.
+#define GTLS_DPP(OP, A, T, X, U) OP " %" #A ", %" #T ", %" #X " row_newbcast:%" #U " row_mask:0xf bank_mask:0xf\n\t"
+#define GTLS_DPP_FMAC_SET(TY, OP)                                                                                  \
+    template <int U>                                                                                               \
+    __device__ __forceinline__ void dpp_fmac(TY(&acc)[1], const TY(&tv)[1], TY x) {                                \
+        asm volatile("s_nop 1\n\t" GTLS_DPP(OP, 0, 1, 2, 3) : "+v"(acc[0]) : "v"(tv[0]), "v"(x), "i"(U));        \
+    }                                                                                                              \
+    template <int U>                                                                                               \
+    __device__ __forceinline__ void dpp_fmac(TY(&acc)[2], const TY(&tv)[2], TY x) {                                \
+        asm volatile("s_nop 1\n\t" GTLS_DPP(OP, 0, 2, 4, 5) GTLS_DPP(OP, 1, 3, 4, 5)                             \
+                     : "+v"(acc[0]), "+v"(acc[1])                                                                  \
+                     : "v"(tv[0]), "v"(tv[1]), "v"(x), "i"(U));                                                    \
+    }                                                                                                              \
+    template <int U>                                                                                               \
+    __device__ __forceinline__ void dpp_fmac(TY(&acc)[4], const TY(&tv)[4], TY x) {                                \
+        asm volatile("s_nop 1\n\t" GTLS_DPP(OP, 0, 4, 8, 9) GTLS_DPP(OP, 1, 5, 8, 9) GTLS_DPP(OP, 2, 6, 8, 9)      \
+                         GTLS_DPP(OP, 3, 7, 8, 9)                                                                  \
+                     : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])                                      \
+                     : "v"(tv[0]), "v"(tv[1]), "v"(tv[2]), "v"(tv[3]), "v"(x), "i"(U));                            \
+    }                                                                                                              \
+    template <int U>                                                                                               \
+    __device__ __forceinline__ void dpp_fmac(TY(&acc)[8], const TY(&tv)[8], TY x) {                                \
+        asm volatile("s_nop 1\n\t" GTLS_DPP(OP, 0, 8, 16, 17) GTLS_DPP(OP, 1, 9, 16, 17)                          \
+                         GTLS_DPP(OP, 2, 10, 16, 17) GTLS_DPP(OP, 3, 11, 16, 17) GTLS_DPP(OP, 4, 12, 16, 17)       \
+                             GTLS_DPP(OP, 5, 13, 16, 17) GTLS_DPP(OP, 6, 14, 16, 17) GTLS_DPP(OP, 7, 15, 16, 17)   \
+                     : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]),         \
+                       "+v"(acc[6]), "+v"(acc[7])                                                                  \
+                     : "v"(tv[0]), "v"(tv[1]), "v"(tv[2]), "v"(tv[3]), "v"(tv[4]), "v"(tv[5]), "v"(tv[6]),         \
+                       "v"(tv[7]), "v"(x), "i"(U));                                                                \
+    }
+GTLS_DPP_FMAC_SET(double, "v_fmac_f64_dpp")
+GTLS_DPP_FMAC_SET(float, "v_fmac_f32_dpp")
+#undef GTLS_DPP_FMAC_SET
+#undef GTLS_DPP
+
+// f(integral_constant<int, k>) for k = 0 .. N - 1, in order.
+template <int N, typename F, int... K>
+__device__ __forceinline__ void unrolled_impl(F&& f, std::integer_sequence<int, K...>) {
+    (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void unrolled(F&& f) {
+    unrolled_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// The 16 template steps of one chunk in ascending order.
+template <typename T, int R, int... U>
+__device__ __forceinline__ void dpp_chunk(T (&acc)[R], const T (&tv)[R], const T (&x)[kSC],
+                                          std::integer_sequence<int, U...>) {
+    (dpp_fmac<U>(acc, tv, x[U]), ...);
+}
+
+// Loads sizeof(V) bytes at a 32-bit byte offset from a wave-uniform base
+// (one address register per lane; the base stays in scalar registers).
+template <typename V>
+__device__ __forceinline__ V load_at(const void* base, uint32_t byte_off) {
+    V v;
+    __builtin_memcpy(&v, (const char*)base + byte_off, sizeof(V));
+    return v;
+}
+
+template <typename T, bool VARW, bool MEAN, int R>
+__device__ Best strided_windows_coop(const SlideItem& si, int64_t m_lo, int64_t m_hi, T* stage, T* stage_w) {
+    constexpr int P = kPiece<T>;
+    constexpr int NP = kSC / P;                     // pieces per row = load instructions per chunk
+    constexpr int OPI = 64 / NP;                    // runs per load instruction
+    const int lane = threadIdx.x & 63;
+    const int a = lane / NP, q = lane % NP;
+    const int64_t s = si.stride, D = si.D;
+    const T* __restrict__ rp = (const T*)si.rp;
+    const T* __restrict__ wp = (const T*)si.wp;
+    const T* __restrict__ tbase = (const T*)si.trow - 2 * kSC;   // the row's 32 leading zeros
+    const int64_t J = D + (R - 1) * s;              // points of a lane's run
+    const int64_t nch = (J + kSC - 1) / kSC;
+    const uint32_t tl = (uint32_t)(lane & 15) * sizeof(T);
+    T* const srow = stage + lane * kStRow<T>;
+    T* const srow_w = VARW ? stage_w + lane * kStRow<T> : nullptr;
+
+    // Template block of window r at chunk c0: lane l holds point c0 - r s + l mod 16.
+    // Blocks wholly before the row read 16 of its 32 leading zeros, blocks at
+    // or past its end the zeros that follow it, so no branch is needed.
+    auto tload = [&](int64_t c0, T (&tv)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t klo = c0 - (int64_t)r * s;
+            const int64_t kc = klo <= -kSC ? -2 * kSC : (klo >= D ? D : klo);
+            tv[r] = load_at<T>(tbase, (uint32_t)(kc + 2 * kSC) * (uint32_t)sizeof(T) + tl);
+        }
+    };
+    auto stage_get = [&](const T* row, T (&x)[kSC]) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const Piece<T> pc = *reinterpret_cast<const Piece<T>*>(row + i * P);
+#pragma unroll
+            for (int e = 0; e < P; ++e) x[i * P + e] = pc.v[e];
+        }
+    };
+    auto products = [&](double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
+                        const T (&xw)[VARW ? kSC : 1], const T (&tv)[R]) {
+        T tq[VARW ? R : 1];
+        if constexpr (VARW) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) tq[r] = tv[r] * tv[r];
+        }
+        if constexpr (sizeof(T) == 8) {
+            dpp_chunk<T, R>(acc, tv, x, std::make_integer_sequence<int, kSC>{});
+            if constexpr (VARW) dpp_chunk<T, R>(bacc, tq, xw, std::make_integer_sequence<int, kSC>{});
+        } else {
+            T ca[R], cq[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) ca[r] = cq[r] = (T)0;
+            dpp_chunk<T, R>(ca, tv, x, std::make_integer_sequence<int, kSC>{});
+            if constexpr (VARW) dpp_chunk<T, R>(cq, tq, xw, std::make_integer_sequence<int, kSC>{});
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r] += (double)ca[r];
+                if constexpr (VARW) bacc[r] += (double)cq[r];
+            }
+        }
+    };
+
+    Best best{-INFINITY, 0.0, -1};
+    for (int64_t g0 = m_lo; g0 < m_hi; g0 += 64 * R) {
+        const int64_t ml = g0 + (int64_t)lane * R;
+        // Byte offset of this lane's piece in the run it loads (lanes past the
+        // range re-read a valid run).  A piece that starts at or past the end
+        // of the padded curve (n + D points) is read from that end instead:
+        // the row holds at least kOverRead finite points there, and such
+        // points meet only template zeros or windows past the task's range.
+        uint32_t cb[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            cb[i] = (uint32_t)((min(g0 + (int64_t)(i * OPI + a) * R, m_hi - 1) * s + q * P) * (int64_t)sizeof(T));
+        const uint32_t cend = (uint32_t)(si.limit * (int64_t)sizeof(T));
+        auto xload = [&](const T* __restrict__ src, int64_t c0, Piece<T> (&nx)[NP]) {
+            const uint32_t co = (uint32_t)c0 * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < NP; ++i) nx[i] = load_at<Piece<T>>(src, min(cb[i] + co, cend));
+        };
+        auto stage_put = [&](T* buf, const Piece<T> (&nx)[NP]) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i)
+                *reinterpret_cast<Piece<T>*>(buf + (i * OPI + a) * kStRow<T> + q * P) = nx[i];
+        };
+        // chunk c0 from the loads in flight to this lane's registers, via LDS
+        auto restage = [&](Piece<T> (&nx)[NP], Piece<T> (&nw)[VARW ? NP : 1], T (&x)[kSC],
+                           T (&xw)[VARW ? kSC : 1]) {
+            wave_sync();
+            stage_put(stage, nx);
+            if constexpr (VARW) stage_put(stage_w, nw);
+            wave_sync();
+            stage_get(srow, x);
+            if constexpr (VARW) stage_get(srow_w, xw);
+        };
+
+        double acc[R], bacc[VARW ? R : 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+        for (int r = 0; r < (VARW ? R : 1); ++r) bacc[r] = 0.0;
+        // Chunk j's curve pieces are requested while chunk j - 2 is being
+        // computed, written to LDS and read back into the other half of x
+        // while chunk j - 1 is computed, and its template blocks are
+        // requested right after chunk j - 2's products; so the products of
+        // chunk j never wait on a load.  Two chunks per trip keep the
+        // halves' indices constant.  Chunks past the run are requested too
+        // (from clamped addresses), so every register is written every trip.
+        T x[2][kSC], xw[2][VARW ? kSC : 1], tv[2][R];
+        Piece<T> nx[NP], nw[VARW ? NP : 1];
+        auto pieces = [&](int64_t j) {
+            xload(rp, j * kSC, nx);
+            if constexpr (VARW) xload(wp, j * kSC, nw);
+        };
+        pieces(0);
+        tload(0, tv[0]);
+        tload(kSC, tv[1]);
+        restage(nx, nw, x[0], xw[0]);
+        pieces(1);
+        auto step = [&](auto kc, int64_t j) {
+            constexpr int k = decltype(kc)::value;
+            restage(nx, nw, x[k ^ 1], xw[k ^ 1]);
+            pieces(j + 2);
+            products(acc, bacc, x[k], xw[k], tv[k]);
+            tload((j + 2) * kSC, tv[k]);
+        };
+        int64_t c = 0;
+        for (; c + 2 <= nch; c += 2) {
+            step(std::integral_constant<int, 0>{}, c);
+            step(std::integral_constant<int, 1>{}, c + 1);
+        }
+        if (c < nch) step(std::integral_constant<int, 0>{}, c);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t m = ml + r;
+            if (m < m_hi) {
+                const int64_t i = m * s;
+                double dchi2, depth;
+                fit<MEAN>(acc[r], VARW ? bacc[r] : si.bconst, window_deficit<T, MEAN>(si.pf, i, D), si.s1, dchi2,
+                          depth);
+                consider(best, dchi2, depth, i);
+            }
+        }
+    }
+    return wave_best(best);
+}
+
+// FP64 takes R in {4, 8} (strided_r_cost), FP32C R in {1, 2, 4} (strided_r
+// with at most 4, the rule the batched kernel shares).
+template <typename T, bool VARW, bool MEAN>
+__device__ Best strided_windows_coop_r(int R, const SlideItem& si, int64_t m_lo, int64_t m_hi, T* stage,
+                                       T* stage_w) {
+    if constexpr (sizeof(T) == 8) {
+        if (R == 8) return strided_windows_coop<T, VARW, MEAN, 8>(si, m_lo, m_hi, stage, stage_w);
+        return strided_windows_coop<T, VARW, MEAN, 4>(si, m_lo, m_hi, stage, stage_w);
+    } else {
+        switch (R) {
+            case 4: return strided_windows_coop<T, VARW, MEAN, 4>(si, m_lo, m_hi, stage, stage_w);
+            case 2: return strided_windows_coop<T, VARW, MEAN, 2>(si, m_lo, m_hi, stage, stage_w);
+            default: return strided_windows_coop<T, VARW, MEAN, 1>(si, m_lo, m_hi, stage, stage_w);
+        }
+    }
+}
+
+// Windows per lane for the cooperative strided slide (FP64, where the sums do
+// not depend on it): R = 4 or 8, whichever needs fewer wave-chunks,
+// waves(R) * chunks(R) = ceil(ceil(nw / R) / 64) * ceil((D + (R - 1) s) / 16);
+// a chunk costs about the same whatever R is (its loads and LDS traffic do
+// not depend on R), so a partly idle wave with more windows per lane can
+// beat full waves with fewer.  (Allowing R = 1 or 2 as well saves under 5 %
+// of the wave-chunks on the 3000-day grid but costs registers: every R is
+// compiled into the one persistent kernel.)  Ties go to R = 4.
+__host__ __device__ __forceinline__ int strided_r_cost(int64_t nw, int64_t s, int64_t d) {
+    int best_r = 4;
+    int64_t best = -1;
+    for (int r = 4; r <= 8; r *= 2) {
+        const int64_t lanes = (nw + r - 1) / r;
+        const int64_t cost = ((lanes + 63) / 64) * ((d + (r - 1) * s + kSC - 1) / kSC);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_r = r;
+        }
+    }
+    return best_r;
+}
+
 // Wave tasks of a strided item: its window groups (64 R windows each) split
 // into at most kTaskMax contiguous runs.
 struct StridedSplit {
@@ -1154,10 +1458,10 @@ struct StridedSplit {
 };
 
 __host__ __device__ __forceinline__ StridedSplit strided_split(int64_t n, int64_t d, int64_t s, int64_t fill,
-                                                               int64_t max_tasks, int rmax) {
+                                                               int64_t max_tasks, int rmax, bool by_cost = false) {
     StridedSplit sp;
     sp.nw = (n + s - 1) / s;
-    sp.R = strided_r(sp.nw, s, d, fill, rmax);
+    sp.R = by_cost ? strided_r_cost(sp.nw, s, d) : strided_r(sp.nw, s, d, fill, rmax);
     const int64_t lanes = (sp.nw + sp.R - 1) / sp.R;
     sp.groups = (lanes + 63) / 64;
     sp.ntask = (int)min(sp.groups, max_tasks);
@@ -1255,7 +1559,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
         if (!duration_valid(period, dur, a.prm)) return 0;
         const int64_t d = points_in(a.n, period, dur);
         const int64_t st = t0_stride(d, a.prm.dt0);
-        return st < 2 ? 0 : strided_split(a.n, d, st, 64, kTaskMax, a.rmax).ntask;
+        return st < 2 ? 0 : strided_split(a.n, d, st, 64, kTaskMax, a.rmax, a.rcost != 0).ntask;
     };
     int32_t sum = 0;
     for (int64_t idx = lo; idx < hi; ++idx) sum += count(idx);
@@ -1287,11 +1591,16 @@ __global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
 
 // Persistent: every wave pops wave tasks from its XCD's queue, then from the
 // others, until all are exhausted.
+// Two waves per SIMD for constant weights (what the loop needs fits the 256
+// registers that allow it; a few task-level values spill); per-point weights
+// double the staged operands, so they keep one wave per SIMD and use the
+// accumulation registers too.
 template <typename T, bool VARW, bool MEAN>
-__global__ __launch_bounds__(kSlideThreads) void k_slide_strided(SlideArgs a) {
-    __shared__ T rings[(kSlideThreads / 64) * 2 * kRing];
+__global__ __launch_bounds__(kSlideThreads, VARW ? 1 : 2) void k_slide_strided(SlideArgs a) {
+    __shared__ __align__(16) T stages[(kSlideThreads / 64) * (VARW ? 2 : 1) * kStage<T>];
     const int lane = threadIdx.x & 63;
-    T* ring = rings + (threadIdx.x >> 6) * 2 * kRing;
+    T* stage = stages + (threadIdx.x >> 6) * (VARW ? 2 : 1) * kStage<T>;
+    T* stage_w = VARW ? stage + kStage<T> : nullptr;
     const int x0 = (int)(blockIdx.x % kXcds);
     for (int k = 0; k < kXcds; ++k) {
         const int x = (x0 + k) % kXcds;
@@ -1316,10 +1625,10 @@ __global__ __launch_bounds__(kSlideThreads) void k_slide_strided(SlideArgs a) {
             it.d = points_in(a.n, it.period, a.durations[it.j]);
             it.stride = t0_stride(it.d, a.prm.dt0);
             const SlideItem si = make_item<T, MEAN>(a, it, VARW);
-            const StridedSplit sp = strided_split(a.n, it.d, it.stride, 64, kTaskMax, a.rmax);
+            const StridedSplit sp = strided_split(a.n, it.d, it.stride, 64, kTaskMax, a.rmax, a.rcost != 0);
             int64_t m_lo, m_hi;
             strided_task_range(sp, t, m_lo, m_hi);
-            const Best b = strided_windows_r<T, VARW, MEAN, 8, true>(sp.R, si, m_lo, m_hi, ring);
+            const Best b = strided_windows_coop_r<T, VARW, MEAN>(sp.R, si, m_lo, m_hi, stage, stage_w);
             if (lane == 0) {
                 ItemBest* o = a.sb + task;
                 o->dchi2 = b.dchi2;
@@ -2021,7 +2330,7 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     dcap = std::max<int64_t>(1, std::min<int64_t>(n, dcap));
     p.dcap = dcap;
     p.ntiles = (int32_t)((n + kTile - 1) / kTile);
-    p.pstride = ((n + dcap + 63) / 64) * 64;
+    p.pstride = ((n + dcap + kOverRead + 63) / 64) * 64;
     size_t per = 2 * sizeof(uint64_t) * (size_t)n + p.esize * (size_t)p.pstride +
                  (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
                  sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles +
@@ -2159,7 +2468,8 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
             k_fold_sort<<<bp, kSortThreads, 0, s>>>(sa);
         }
         SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.prm, rpad, wpad, pfx, pl.pstride,
-                     misc, table, bsum, s1sum, items, pl.ntiles, toff, tmap, sb, queue, pl.f32 ? 4 : 8};
+                     misc, table, bsum, s1sum, items, pl.ntiles, toff, tmap, sb, queue, pl.f32 ? 4 : 8,
+                     pl.f32 ? 0 : 1};
         const unsigned grid = (unsigned)bp * (unsigned)a.n_durations * (unsigned)pl.ntiles;
         if (pl.f32) launch_slides<float>(ctx, la, grid, strided, varw, pl.mean, ctx->num_cus, s);
         else launch_slides<double>(ctx, la, grid, strided, varw, pl.mean, ctx->num_cus, s);
