@@ -277,11 +277,9 @@ struct PadOut {
     bool f32;
 };
 
-// Writes the residual (and weight) of input point idx at padded position
-// pos and, when pos + n is still inside the padding, at pos + n.
-__device__ __forceinline__ void pad_store(const PadOut& po, int64_t n, int64_t pos, uint32_t idx) {
-    const double rv = po.r[idx];
-    const double wv = po.wpad ? po.w[idx] : 0.0;
+// Writes a residual rv (and weight wv) at padded position pos and, when
+// pos + n is still inside the padding, at pos + n.
+__device__ __forceinline__ void pad_put(const PadOut& po, int64_t n, int64_t pos, double rv, double wv) {
     const bool twice = pos + n < po.npad;
     if (po.f32) {
         float* rp = (float*)po.rpad;
@@ -302,6 +300,11 @@ __device__ __forceinline__ void pad_store(const PadOut& po, int64_t n, int64_t p
             if (twice) wp[pos + n] = wv;
         }
     }
+}
+
+// The residual (and weight) of input point idx at padded position pos.
+__device__ __forceinline__ void pad_store(const PadOut& po, int64_t n, int64_t pos, uint32_t idx) {
+    pad_put(po, n, pos, po.r[idx], po.wpad ? po.w[idx] : 0.0);
 }
 
 // Phase order of n points at `period`: A[k] = (phase key << 32 | index) of
@@ -375,13 +378,17 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
                 const int64_t idx = seg0 + e * 64 + lane;
                 const bool active = idx < n;
                 const uint32_t d = active ? (uint32_t)(item[e] >> shift) & 255u : 0u;
-                uint64_t peers = __ballot(active);
+                // lanes whose digit differs in some bit: ballot(bit) XOR this
+                // lane's bit spread over 32 bits, OR-ed over the 8 bits
+                uint32_t dlo = 0u, dhi = 0u;
 #pragma unroll
                 for (int b = 0; b < 8; ++b) {
-                    const bool bit = (d >> b) & 1u;
-                    const uint64_t m = __ballot(bit);
-                    peers &= bit ? m : ~m;
+                    const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+                    const uint64_t m = __ballot(sb != 0u);
+                    dlo |= (uint32_t)m ^ sb;
+                    dhi |= (uint32_t)(m >> 32) ^ sb;
                 }
+                const uint64_t peers = __ballot(active) & ~(((uint64_t)dhi << 32) | dlo);
                 const uint32_t before = __popcll(peers & lt_mask);
                 uint32_t cnt = 0;
                 if (active) cnt = sh.wcnt[wave][d];
@@ -451,9 +458,20 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
     // A: order by 24-bit key, equal keys in input order.  Equal keys may hide
     // different phases: order each run by the full FP64 phase, then input
     // index (insertion sort; runs are short), and rewrite its padded copies.
-    for (int64_t k = tid; k + 1 < n; k += NT) {
-        const uint32_t kk = (uint32_t)(A[k] >> 32);
-        if (kk == (uint32_t)(A[k + 1] >> 32) && (k == 0 || (uint32_t)(A[k - 1] >> 32) != kk)) {
+    // Each thread checks 8 consecutive positions per trip, their 10 keys
+    // (positions k0 - 1 .. k0 + 8; none outside [0, n)) loaded at once.
+    for (int64_t k0 = (int64_t)tid * 8; k0 + 1 < n; k0 += (int64_t)NT * 8) {
+        uint32_t kv[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const int64_t p = k0 - 1 + q;
+            kv[q] = (p >= 0 && p < n) ? (uint32_t)(A[p] >> 32) : 0xffffffffu;   // keys are < 2^24
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t k = k0 + j;
+            const uint32_t kk = kv[j + 1];
+            if (k + 1 >= n || kk != kv[j + 2] || kv[j] == kk) continue;
             int64_t e = k + 1;
             while (e + 1 < n && (uint32_t)(A[e + 1] >> 32) == kk) ++e;
             for (int64_t x = k + 1; x <= e; ++x) {
