@@ -177,7 +177,7 @@ gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux
  * (curve, period) work items (Sect. 2.3-2.4 per curve).
  *   offsets [n_curves + 1], host: curve c owns points
  *     [offsets[c], offsets[c + 1]) of time/flux/dy; offsets[0] = 0, each
- *     curve has 3 <= n_c < 2^31 points (otherwise the rules of tls_search).
+ *     curve has 3 <= n_c <= 2^27 points (same rules as tls_search).
  *   period_offsets [n_curves + 1], host: curve c's grid is
  *     periods[period_offsets[c] .. period_offsets[c + 1]), at least one
  *     period, strictly increasing; period_offsets[0] = 0.

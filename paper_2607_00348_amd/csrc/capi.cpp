@@ -284,7 +284,7 @@ static gtls_status check_batch_sizes(gtls_ctx* ctx, const int64_t* offsets, int3
     if (offsets[0] != 0 || poff[0] != 0) return fail(ctx, GTLS_EINVAL, "offsets must start at 0");
     for (int32_t c = 0; c < nc; ++c) {
         const int64_t n = offsets[c + 1] - offsets[c];
-        if (n < 3 || n > 0x7fffffff) return fail(ctx, GTLS_EINVAL, "each curve needs 3 <= n < 2^31 points");
+        if (n < 3 || n > (1 << 27)) return fail(ctx, GTLS_EINVAL, "each curve needs 3 <= n <= 2^27 points");
         if (poff[c + 1] - poff[c] < 1) return fail(ctx, GTLS_EINVAL, "each curve needs at least one period");
     }
     if (poff[nc] > 0x7fffffff) return fail(ctx, GTLS_EINVAL, "too many periods in one batch");

@@ -967,26 +967,19 @@ __device__ Best slide_unit_tile(const SlideItem& si, int64_t i0, T* x_sh, T* xw_
 // lane owns R consecutive windows m, m + 1, ..., m + R - 1, which start s
 // points apart, so one curve point x[m s + j] serves all of them: window r
 // takes it with template point j - r s.  The lane walks j upward over its
-// own contiguous run of the padded curve in chunks of 16 (the next chunk is
-// loaded while this one is used); window r skips the chunks outside
-// [r s, r s + D) and reads zeros for template points outside [0, D) in the
-// two partial ones (x * 0 leaves the running sum unchanged exactly), so
-// every window still sums its D products in ascending template order.  The
-// template streams through a per-wave LDS ring: each chunk appends the next
-// 16 row points (fetched one chunk ahead), and window r reads its 16 from
-// the ring with in-order LDS loads.  The ring is written twice (at p and
-// p + kRing) so a 16-point read never wraps; it must hold the last
-// (R - 1) s + 32 points, which caps R.
+// own contiguous run of the padded curve in chunks of 16 points.
 constexpr int kSC = 16;                             // j steps per chunk
 constexpr int kTaskMax = 16;                        // wave tasks per strided item
-constexpr int kRing = 1024;                         // template ring points per wave (stored twice)
+constexpr int kRunCap = 1024;                       // FP32C rule: (R - 1) s + 32 <= kRunCap
 
-// Windows per lane: the largest of 8, 4, 2 (at most rmax) that still gives
-// `fill` lanes a window each, when consecutive windows overlap (s < D);
-// else 1.
+// Windows per lane for FP32C, the rule the single-curve and batched searches
+// share (their float partial sums depend on R): the largest of 8, 4, 2 (at
+// most rmax) that still gives `fill` lanes a window each and keeps a lane's
+// run within kRunCap points beyond D, when consecutive windows overlap
+// (s < D); else 1.
 __host__ __device__ __forceinline__ int strided_r(int64_t nw, int64_t s, int64_t d, int64_t fill, int rmax) {
     if (s >= d) return 1;
-    auto fits = [&](int r) { return nw >= r * fill && (r - 1) * s + 2 * kSC <= kRing; };
+    auto fits = [&](int r) { return nw >= r * fill && (r - 1) * s + 2 * kSC <= kRunCap; };
     if (rmax >= 8 && fits(8)) return 8;
     if (rmax >= 4 && fits(4)) return 4;
     if (fits(2)) return 2;
@@ -1009,181 +1002,15 @@ __device__ __forceinline__ Best wave_best(Best best) {
     return best;
 }
 
-// 16 points of a lane's run from index c0 on; points at or past `avail`
-// (the end of the padded curve) read as zero.
-template <typename T>
-__device__ __forceinline__ void run_chunk(T (&v)[kSC], const T* __restrict__ p, int64_t c0, int64_t avail) {
-    if (c0 + kSC <= avail) {
-#pragma unroll
-        for (int u = 0; u < kSC; ++u) v[u] = p[c0 + u];
-    } else {
-#pragma unroll
-        for (int u = 0; u < kSC; ++u) {
-            const bool ok = c0 + u < avail;
-            const T val = p[ok ? c0 + u : 0];
-            v[u] = ok ? val : (T)0;
-        }
-    }
-}
-
-template <typename T, bool VARW, int R>
-__device__ __forceinline__ void strided_chunk(double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
-                                              const T (&xw)[VARW ? kSC : 1], const T* ring, int64_t c0, int64_t s,
-                                              int64_t D) {
-    // window r + 1's template block is read while window r's products run
-    // (ring reads are always in range; inactive windows just skip the math)
-    T tn[kSC];
-    {
-        const T* tp = ring + (c0 & (kRing - 1));
-#pragma unroll
-        for (int u = 0; u < kSC; ++u) tn[u] = tp[u];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t klo = c0 - (int64_t)r * s;     // template index of x[0] for window r
-        T t[kSC];
-#pragma unroll
-        for (int u = 0; u < kSC; ++u) t[u] = tn[u];
-        if (r + 1 < R) {
-            const T* tp = ring + ((klo - s) & (kRing - 1));
-#pragma unroll
-            for (int u = 0; u < kSC; ++u) tn[u] = tp[u];
-        }
-        if (klo > -kSC && klo < D) {
-            if constexpr (sizeof(T) == 8) {
-#pragma unroll
-                for (int u = 0; u < kSC; ++u) {
-                    acc[r] = fma((double)x[u], (double)t[u], acc[r]);
-                    if constexpr (VARW) bacc[r] = fma((double)xw[u], (double)(t[u] * t[u]), bacc[r]);
-                }
-            } else {
-                T ca = (T)0, cb = (T)0;
-#pragma unroll
-                for (int u = 0; u < kSC; ++u) {
-                    ca = fma(x[u], t[u], ca);
-                    if constexpr (VARW) cb = fma(xw[u], t[u] * t[u], cb);
-                }
-                acc[r] += (double)ca;
-                if constexpr (VARW) bacc[r] += (double)cb;
-            }
-        }
-    }
-}
-
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Windows [m_lo, m_hi) of one item on one wave; returns the wave's first
-// best on every lane.  ring: this wave's 2 kRing LDS points.  DB: load the
-// next chunk while this one is used.
-template <typename T, bool VARW, bool MEAN, int R, bool DB>
-__device__ Best strided_windows(const SlideItem& si, int64_t m_lo, int64_t m_hi, T* ring) {
-    const int lane = threadIdx.x & 63;
-    const int64_t s = si.stride, D = si.D;
-    const T* __restrict__ trow = (const T*)si.trow;
-    const int64_t J = D + (R - 1) * s;              // j steps of a lane
-    // ring append: lanes 0..15 write template point c0 + lane (zero past D)
-    auto tfetch = [&](int64_t c0) -> T {
-        const int64_t k = c0 + lane;
-        return (lane < kSC && k < D) ? trow[k] : (T)0;
-    };
-    auto tput = [&](int64_t c0, T v) {
-        if (lane < kSC) {
-            const int p = (int)((c0 + lane) & (kRing - 1));
-            ring[p] = v;
-            ring[p + kRing] = v;
-        }
-    };
-    Best best{-INFINITY, 0.0, -1};
-    for (int64_t g0 = m_lo; g0 < m_hi; g0 += 64 * R) {
-        const int64_t ml = g0 + (int64_t)lane * R;
-        const int64_t base = min(ml, m_hi - 1) * s;  // lanes past the range re-read a valid run
-        const int64_t avail = si.limit - base;
-        const T* __restrict__ xp = (const T*)si.rp + base;
-        const T* __restrict__ xq = VARW ? (const T*)si.wp + base : nullptr;
-        double acc[R], bacc[VARW ? R : 1];
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0.0;
-#pragma unroll
-        for (int r = 0; r < (VARW ? R : 1); ++r) bacc[r] = 0.0;
-        // template points -16..-1 read as zero until the ring wraps past them
-        wave_sync();
-        if (lane < kSC) {
-            ring[kRing - kSC + lane] = (T)0;
-            ring[2 * kRing - kSC + lane] = (T)0;
-        }
-        T tcur = tfetch(0);
-        if constexpr (!DB) {
-            T va[kSC], wa[VARW ? kSC : 1];
-            for (int64_t c0 = 0; c0 < J; c0 += kSC) {
-                run_chunk(va, xp, c0, avail);
-                if constexpr (VARW) run_chunk(wa, xq, c0, avail);
-                tput(c0, tcur);
-                wave_sync();
-                tcur = tfetch(c0 + kSC);
-                strided_chunk<T, VARW, R>(acc, bacc, va, wa, ring, c0, s, D);
-                wave_sync();
-            }
-        } else {
-            T va[kSC], vb[kSC], wa[VARW ? kSC : 1], wb[VARW ? kSC : 1];
-            run_chunk(va, xp, 0, avail);
-            if constexpr (VARW) run_chunk(wa, xq, 0, avail);
-            for (int64_t c0 = 0; c0 < J; c0 += 2 * kSC) {
-                const bool more = c0 + kSC < J;
-                if (more) {
-                    run_chunk(vb, xp, c0 + kSC, avail);
-                    if constexpr (VARW) run_chunk(wb, xq, c0 + kSC, avail);
-                }
-                tput(c0, tcur);
-                wave_sync();
-                tcur = tfetch(c0 + kSC);
-                strided_chunk<T, VARW, R>(acc, bacc, va, wa, ring, c0, s, D);
-                wave_sync();
-                if (!more) break;
-                if (c0 + 2 * kSC < J) {
-                    run_chunk(va, xp, c0 + 2 * kSC, avail);
-                    if constexpr (VARW) run_chunk(wa, xq, c0 + 2 * kSC, avail);
-                }
-                tput(c0 + kSC, tcur);
-                wave_sync();
-                tcur = tfetch(c0 + 2 * kSC);
-                strided_chunk<T, VARW, R>(acc, bacc, vb, wb, ring, c0 + kSC, s, D);
-                wave_sync();
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t m = ml + r;
-            if (m < m_hi) {
-                const int64_t i = m * s;
-                double dchi2, depth;
-                fit<MEAN>(acc[r], VARW ? bacc[r] : si.bconst, window_deficit<T, MEAN>(si.pf, i, D), si.s1, dchi2,
-                          depth);
-                consider(best, dchi2, depth, i);
-            }
-        }
-    }
-    return wave_best(best);
-}
-
-template <typename T, bool VARW, bool MEAN, int RMAX, bool DB>
-__device__ Best strided_windows_r(int R, const SlideItem& si, int64_t m_lo, int64_t m_hi, T* ring) {
-    switch (R) {
-        case 8:
-            if constexpr (RMAX >= 8) return strided_windows<T, VARW, MEAN, 8, DB>(si, m_lo, m_hi, ring);
-            [[fallthrough]];
-        case 4: return strided_windows<T, VARW, MEAN, 4, DB>(si, m_lo, m_hi, ring);
-        case 2: return strided_windows<T, VARW, MEAN, 2, DB>(si, m_lo, m_hi, ring);
-        default: return strided_windows<T, VARW, MEAN, 1, DB>(si, m_lo, m_hi, ring);
-    }
-}
-
-// Strided windows with coalesced curve loads (the persistent single-curve
-// kernel).  Same windows, chunks and per-window sums as strided_windows, with
-// two changes to where the operands come from:
+// Windows [m_lo, m_hi) of one strided item on one wave (the persistent
+// single-curve kernel and the batched megakernel); returns the wave's first
+// best on every lane.  Operands:
 //  - each 16-point chunk of the 64 lanes' runs is loaded cooperatively: 8
 //    lanes (FP64) or 4 lanes (FP32) read one lane's chunk as 16-byte pieces,
 //    so one load instruction touches 8 or 16 runs instead of 64; the pieces
@@ -1193,10 +1020,9 @@ __device__ Best strided_windows_r(int R, const SlideItem& si, int64_t m_lo, int6
 //    the table with lane l holding point l mod 16, and each multiply-add takes
 //    its template point by a DPP row broadcast from lane u of the 16-lane row,
 //    so no template value passes through LDS.
-// The next chunk's loads are issued before this chunk's products.  Windows
-// outside their span in a chunk multiply by template zeros (the row guards,
-// or an explicit zero when the block lies wholly outside the row), which
-// leaves their sums unchanged exactly.
+// Windows outside their span in a chunk multiply template zeros (the row
+// guards), which leaves their sums unchanged exactly (every curve value is
+// finite), so every window sums its D products in ascending template order.
 template <typename T>
 constexpr int kPiece = 16 / (int)sizeof(T);                  // points per 16-byte piece
 template <typename T>
@@ -1428,13 +1254,16 @@ __device__ Best strided_windows_coop(const SlideItem& si, int64_t m_lo, int64_t 
     return wave_best(best);
 }
 
-// FP64 takes R in {4, 8} (strided_r_cost), FP32C R in {1, 2, 4} (strided_r
-// with at most 4, the rule the batched kernel shares).
-template <typename T, bool VARW, bool MEAN>
+// FP64 takes R in {4, 8} (strided_r_cost; RMAX = 4 for the batched
+// megakernel, whose other phases hold many registers), FP32C R in {1, 2, 4}
+// (strided_r with at most 4, the rule both searches share).
+template <typename T, bool VARW, bool MEAN, int RMAX = 8>
 __device__ Best strided_windows_coop_r(int R, const SlideItem& si, int64_t m_lo, int64_t m_hi, T* stage,
                                        T* stage_w) {
     if constexpr (sizeof(T) == 8) {
-        if (R == 8) return strided_windows_coop<T, VARW, MEAN, 8>(si, m_lo, m_hi, stage, stage_w);
+        if constexpr (RMAX >= 8) {
+            if (R == 8) return strided_windows_coop<T, VARW, MEAN, 8>(si, m_lo, m_hi, stage, stage_w);
+        }
         return strided_windows_coop<T, VARW, MEAN, 4>(si, m_lo, m_hi, stage, stage_w);
     } else {
         switch (R) {
@@ -1479,7 +1308,7 @@ __host__ __device__ __forceinline__ StridedSplit strided_split(int64_t n, int64_
                                                                int64_t max_tasks, int rmax, bool by_cost = false) {
     StridedSplit sp;
     sp.nw = (n + s - 1) / s;
-    sp.R = by_cost ? strided_r_cost(sp.nw, s, d) : strided_r(sp.nw, s, d, fill, rmax);
+    sp.R = by_cost ? (rmax >= 8 ? strided_r_cost(sp.nw, s, d) : 4) : strided_r(sp.nw, s, d, fill, rmax);
     const int64_t lanes = (sp.nw + sp.R - 1) / sp.R;
     sp.groups = (lanes + 63) / 64;
     sp.ntask = (int)min(sp.groups, max_tasks);
@@ -2148,6 +1977,10 @@ __global__ __launch_bounds__(kBatchThreads, 2) void k_batch(BatchArgs a) {
         const PadOut po{a.r + o0, a.w + o0, rpad, varw ? wpad : nullptr, npad, sizeof(T) == 4};
         fold_sort_core<kBatchThreads, false>(a.t + o0, n, period, A, B, po, ssh);
         pad_prefix<kBatchThreads>(A, n, npad, a.u + o0, pfx, sizeof(T) == 4, ssh);
+        for (int64_t k = npad + tid; k < npad + kOverRead; k += kBatchThreads) {
+            ((T*)rpad)[k] = (T)0;
+            if (varw) ((T*)wpad)[k] = (T)0;
+        }
         // Constant-weight b per duration: one sequential chain per lane.
         if (!varw) {
             for (int j = tid; j < a.nd; j += kBatchThreads) {
@@ -2198,20 +2031,20 @@ __global__ __launch_bounds__(kBatchThreads, 2) void k_batch(BatchArgs a) {
                     if (tb.dchi2 > jb.dchi2) jb = tb;
                 }
             } else {
-                // the item's window groups split into one contiguous run per wave
+                // the item's window groups split into one contiguous run per wave, each computed by the
+                // cooperative strided routine of the single-curve search with the same windows-per-lane
+                // rule (FP32C flushes its float partial sums at chunk boundaries that depend on a window's
+                // place in its lane, so both searches must choose the same R to give identical results)
                 const int wave = tid >> 6;
-                // At most 4 windows per lane: the megakernel's other phases already hold many registers.
-                // FP32C flushes its float partial sums at chunk boundaries that depend on the window's
-                // place in its lane, so it uses the single-curve rule (fill one wave, R <= 4) to give
-                // identical results.
-                const StridedSplit sp = strided_split(n, si.D, si.stride, sizeof(T) == 4 ? 64 : kBatchThreads,
-                                                      kBatchThreads / 64, 4);
+                const StridedSplit sp = strided_split(n, si.D, si.stride, 64, kBatchThreads / 64, 4, sizeof(T) == 8);
                 int64_t m_lo = 0, m_hi = 0;
                 if (wave < sp.ntask) strided_task_range(sp, wave, m_lo, m_hi);
                 Best lb;
-                T* ring = reinterpret_cast<T*>(dyn) + wave * 2 * kRing;
-                if (ANYVARW && varw) lb = strided_windows_r<T, ANYVARW, MEAN, 4, false>(sp.R, si, m_lo, m_hi, ring);
-                else lb = strided_windows_r<T, false, MEAN, 4, false>(sp.R, si, m_lo, m_hi, ring);
+                T* stage = reinterpret_cast<T*>(dyn) + wave * (ANYVARW ? 2 : 1) * kStage<T>;
+                if (ANYVARW && varw)
+                    lb = strided_windows_coop_r<T, ANYVARW, MEAN, 4>(sp.R, si, m_lo, m_hi, stage, stage + kStage<T>);
+                else
+                    lb = strided_windows_coop_r<T, false, MEAN, 4>(sp.R, si, m_lo, m_hi, stage, nullptr);
                 jb = block_best(lb, bs.red);
             }
             if (jb.dchi2 > pbest.dchi2) {
@@ -2514,8 +2347,8 @@ size_t batch_lds_bytes() {
     const size_t es = sizeof(T), mult = ANYVARW ? 2 : 1;
     const size_t sort = sizeof(SortShared<kBatchThreads>);
     const size_t unit = (size_t)xpad<T>(kXs) * es * mult;
-    const size_t ring = (size_t)(kBatchThreads / 64) * 2 * kRing * es;
-    return std::max(sort, std::max(unit, ring));
+    const size_t stage = (size_t)(kBatchThreads / 64) * mult * kStage<T> * es;
+    return std::max(sort, std::max(unit, stage));
 }
 
 template <typename T, bool MEAN, bool ANYVARW>
@@ -2576,7 +2409,7 @@ hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& h) {
     std::vector<int64_t> qoff(nc + 1, 0);
     for (int q = 0; q < nc; ++q) qoff[q + 1] = qoff[q] + (h.poffsets[order[q] + 1] - h.poffsets[order[q]]);
     const int64_t total_points = h.offsets[nc], total_items = qoff[nc];
-    const int64_t pstride = ((n_max + dcap + 63) / 64) * 64;
+    const int64_t pstride = ((n_max + dcap + kOverRead + 63) / 64) * 64;
 
     // Per-curve device arrays: offsets, poffsets, order, qoff, cmisc, cevals, queue, w, r, u, s1sum.
     size_t o = 0;
