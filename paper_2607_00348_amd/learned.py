@@ -158,6 +158,28 @@ def run(n_train: int, n_test: int, steps: int, k: int = 32, seed: int = 0, accep
         fb_best, _, _ = batched_search(ctx, [test_c[i] for i in fall], [grid] * len(fall), durs, tm)
         final[fall] = fb_best
     t_fallback = time.perf_counter() - t0
+    # Recall / speed-up trade-off.  A curve that falls back gets exactly the
+    # full-grid result, so for any threshold the final best period is known
+    # from the two searches already run; the fallback time is the measured
+    # full-grid time scaled by the fraction of curves (all test curves have
+    # the same length).  Larger k re-runs only the pruned search.
+    tradeoff = []
+    for kk in sorted({k, 2 * k, 3 * k}):
+        if kk == k:
+            pb, ps, tp = pr_best, pr_sde, t_pruned
+        else:
+            t1 = time.perf_counter()
+            topk = gtls.gtls_cnn_topk(net, views_of(ctx, test_c), kk)
+            subk = [grid[np.isin(gbin, topk[i])] for i in range(n_test)]
+            subk = [q if len(q) else grid[:1] for q in subk]
+            pb, ps, _ = batched_search(ctx, test_c, subk, durs, tm)
+            tp = time.perf_counter() - t1
+        for thr in (7.0, 8.0, 9.0, 10.0, 12.0, 15.0, 20.0):
+            fb = ps < thr
+            fin = np.where(fb, te_best, pb)
+            tradeoff.append({"k": kk, "accept_sde": thr, "fallback_fraction": float(fb.mean()),
+                             "recall_best_period": float(np.mean(fin == te_best)),
+                             "speedup_est": t_full / (tp + fb.mean() * t_full)})
     prior = np.argsort(-np.bincount(tr_lab, minlength=N_BINS), kind="stable")[:k]
     strong = te_sde >= 7.0
     out = {
@@ -178,6 +200,7 @@ def run(n_train: int, n_test: int, steps: int, k: int = 32, seed: int = 0, accep
         "curves_per_hour_full": 3600.0 * n_test / t_full,
         "curves_per_hour_learned": 3600.0 * n_test / (t_pruned + t_fallback),
         "speedup": t_full / (t_pruned + t_fallback),
+        "tradeoff": tradeoff,
     }
     net.close()
     ctx.close()
