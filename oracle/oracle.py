@@ -97,6 +97,10 @@ def lib():
                                         ctypes.c_int, dp, ip, ip, dp, dp, dp, lp]
         L.oracle_sde.restype = ctypes.c_int
         L.oracle_sde.argtypes = [dp, ctypes.c_int32, ctypes.c_int32, dp, dp, dp, ip]
+        L.oracle_transit_stats.restype = ctypes.c_int
+        L.oracle_transit_stats.argtypes = [dp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int64,
+                                           ctypes.c_int64, dp, ctypes.c_int32, dp, lp, ctypes.c_int64, lp, dp,
+                                           dp, dp, lp]
         _lib = L
     return _lib
 
@@ -343,3 +347,32 @@ def tls_search_two_stage(t, y, dy, periods, durations, tmpl, dt0: float, n_refin
         res.n_evals += fine.n_evals
         refined[pick] = True
     return res, sde(res.chi2, window), refined
+
+
+TRANSIT_STATS_KEYS = ("snr", "depth", "depth_odd", "depth_even", "sigma_odd", "sigma_even", "odd_even_sigma",
+                      "phase_mid")
+
+
+def transit_stats(t, y, dy, period: float, d: int, start: int, tmpl, max_transits: int = 1 << 20):
+    """SNR, per-transit and odd/even depths of the window of d points that
+    starts at sorted position `start` of the curve folded at `period` (the
+    reading is stated at oracle_transit_stats in tls_oracle.c).  Returns
+    (stats dict, per-transit dict of arrays: epoch, t_mid, depth, sigma,
+    count)."""
+    t, y, dy, tmpl = _f64(t), _f64(y), _f64(dy), _f64(tmpl)
+    st = np.zeros(8)
+    ints = np.zeros(3, dtype=np.int64)
+    cap = int(max_transits)
+    ep = np.zeros(cap, dtype=np.int64)
+    tm, de, sg = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    cn = np.zeros(cap, dtype=np.int64)
+    lp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = lib().oracle_transit_stats(_dp(t), _dp(y), _dp(dy), len(t), float(period), int(d), int(start),
+                                    _dp(tmpl), len(tmpl), _dp(st), lp(ints), cap, lp(ep), _dp(tm), _dp(de),
+                                    _dp(sg), lp(cn))
+    if rc != 0:
+        raise ValueError("more transits than max_transits")
+    stats = dict(zip(TRANSIT_STATS_KEYS, (float(v) for v in st)))
+    stats.update(n_in=int(ints[0]), n_transits=int(ints[1]), first_epoch=int(ints[2]))
+    k = int(ints[1])
+    return stats, {"epoch": ep[:k], "t_mid": tm[:k], "depth": de[:k], "sigma": sg[:k], "count": cn[:k]}

@@ -354,3 +354,108 @@ int oracle_sde(const double *chi2, int32_t n, int32_t window,
     *best = b;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Transit statistics at one window: the SNR and the per-transit and
+ * odd/even depths the paper names (Sect. 1 and 2.5, SDE and SNR thresholds
+ * of Sect. 3) without giving formulas; the reading is:
+ *   - the window is the search's: padded positions start .. start + d - 1 of
+ *     the curve folded at `period`, sorted position p mod n, "wrapped" when
+ *     p >= n (the padding repeats the start of the folded curve);
+ *   - window point k, input index idx, belongs to the transit of epoch
+ *     e_k = floor(t_idx / period) - wrapped;
+ *   - per epoch, over its points in ascending k, c_e = sum fma(r, s_k, .)
+ *     and b_e = sum fma(w, s_k^2, .) with w = 1/dy^2, r = w (1 - y) and s the
+ *     d-point template; depth_e = c_e / b_e, sigma_e = 1 / sqrt(b_e);
+ *   - odd epochs, even epochs and all epochs pool c and b in ascending epoch
+ *     order into the same depth and sigma; the odd/even mismatch is
+ *     |depth_odd - depth_even| / sqrt(sigma_odd^2 + sigma_even^2);
+ *   - SNR = max(C, 0) / sqrt(B) over all epochs: the fitted depth over its
+ *     standard error, which is sqrt(chi2_0 - chi2) of the weighted
+ *     least-squares fit of the window (Sect. 2.3.4);
+ *   - the mid-transit time of epoch e is (e + phase_mid) period, phase_mid
+ *     the phase of the window's middle point (position start + floor(d/2)),
+ *     plus 1 when that position is wrapped.
+ * stats[8] = snr, depth, depth_odd, depth_even, sigma_odd, sigma_even,
+ * odd_even_sigma, phase_mid (NaN where a side has no transit);
+ * ints[3] = points in the window, transits (epochs with points), first
+ * epoch.  The per-transit arrays receive the epochs with points in
+ * ascending order, at most max_transits of them.  Returns 1 when more
+ * transits exist than max_transits, else 0.                              */
+int oracle_transit_stats(const double *t, const double *y, const double *dy, int64_t n,
+                         double period, int64_t d, int64_t start,
+                         const double *tmpl, int32_t n_tmpl, double *stats, int64_t *ints,
+                         int64_t max_transits, int64_t *epoch, double *t_mid, double *depth,
+                         double *sigma, int64_t *count)
+{
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *s = (double *)malloc(sizeof(double) * (size_t)d);
+    int64_t *ek = (int64_t *)malloc(sizeof(int64_t) * (size_t)d);
+    oracle_fold_sort(t, n, period, perm);
+    oracle_resample(tmpl, n_tmpl, d, s);
+    int64_t emin = 0, emax = 0;
+    for (int64_t k = 0; k < d; ++k) {
+        int64_t p = start + k;
+        int wrapped = p >= n;
+        int32_t idx = perm[wrapped ? p - n : p];
+        ek[k] = (int64_t)floor(t[idx] / period) - wrapped;
+        if (k == 0 || ek[k] < emin) emin = ek[k];
+        if (k == 0 || ek[k] > emax) emax = ek[k];
+    }
+    int64_t nep = emax - emin + 1;
+    double *ce = (double *)calloc((size_t)nep, sizeof(double));
+    double *be = (double *)calloc((size_t)nep, sizeof(double));
+    int64_t *ne = (int64_t *)calloc((size_t)nep, sizeof(int64_t));
+    for (int64_t k = 0; k < d; ++k) {
+        int64_t p = start + k;
+        int32_t idx = perm[p >= n ? p - n : p];
+        double w = 1.0 / (dy[idx] * dy[idx]);
+        double r = w * (1.0 - y[idx]);
+        int64_t j = ek[k] - emin;
+        ce[j] = fma(r, s[k], ce[j]);
+        double sk2 = s[k] * s[k];
+        be[j] = fma(w, sk2, be[j]);
+        ne[j] += 1;
+    }
+    int64_t pm = start + d / 2;
+    double phase_mid = oracle_phase(t[perm[pm >= n ? pm - n : pm]], period) + (pm >= n ? 1.0 : 0.0);
+    double c_all = 0.0, b_all = 0.0, c_odd = 0.0, b_odd = 0.0, c_even = 0.0, b_even = 0.0;
+    int64_t nt = 0;
+    for (int64_t j = 0; j < nep; ++j) {
+        if (ne[j] == 0) continue;
+        int64_t e = emin + j;
+        if (nt < max_transits) {
+            epoch[nt] = e;
+            t_mid[nt] = ((double)e + phase_mid) * period;
+            depth[nt] = ce[j] / be[j];
+            sigma[nt] = 1.0 / sqrt(be[j]);
+            count[nt] = ne[j];
+        }
+        ++nt;
+        c_all += ce[j];
+        b_all += be[j];
+        if (((e % 2) + 2) % 2 == 1) {
+            c_odd += ce[j];
+            b_odd += be[j];
+        } else {
+            c_even += ce[j];
+            b_even += be[j];
+        }
+    }
+    double d_odd = b_odd > 0.0 ? c_odd / b_odd : NAN, s_odd = b_odd > 0.0 ? 1.0 / sqrt(b_odd) : NAN;
+    double d_even = b_even > 0.0 ? c_even / b_even : NAN, s_even = b_even > 0.0 ? 1.0 / sqrt(b_even) : NAN;
+    stats[0] = (c_all > 0.0 ? c_all : 0.0) / sqrt(b_all);
+    stats[1] = c_all / b_all;
+    stats[2] = d_odd;
+    stats[3] = d_even;
+    stats[4] = s_odd;
+    stats[5] = s_even;
+    stats[6] = (b_odd > 0.0 && b_even > 0.0) ? fabs(d_odd - d_even) / sqrt(s_odd * s_odd + s_even * s_even) : NAN;
+    stats[7] = phase_mid;
+    ints[0] = d;
+    ints[1] = nt;
+    ints[2] = nt > 0 ? emin : 0;
+    for (int64_t j = 0; j < nep; ++j) if (ne[j] > 0) { ints[2] = emin + j; break; }
+    free(perm); free(s); free(ek); free(ce); free(be); free(ne);
+    return nt > max_transits ? 1 : 0;
+}

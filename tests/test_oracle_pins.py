@@ -448,3 +448,91 @@ def test_two_stage_limits(oracle):
     # the refined set is the 15 largest first-stage SDE values
     _, _, sdec, _ = oracle.sde(coarse.chi2)
     assert np.min(sdec[refk]) >= np.max(sdec[~refk])
+
+
+# ---------------------------------------------------------------------------
+# Transit statistics at one window (SNR, per-transit and odd/even depths).
+
+def _stats_case(oracle, seed=5, n=900, period=3.7, d=23, start=None):
+    g = np.random.default_rng(seed)
+    t = np.sort(g.uniform(0.0, 60.0, n))
+    y = 1.0 + 1e-3 * g.standard_normal(n)
+    dy = np.exp(g.uniform(np.log(5e-4), np.log(2e-3), n))
+    tm = oracle.template_quadratic(0.4, 0.25, 0.05, 0.0, 256)
+    if start is None:
+        start = n - d // 2          # a window that wraps round phase 0
+    return t, y, dy, period, d, start, tm
+
+
+def test_transit_stats_brute_force(oracle):
+    """Per-transit depths and counts against numpy sums over the window
+    points grouped by transit; SNR^2 against chi2_0 minus the literal chi2 of
+    the window at the fitted depth."""
+    t, y, dy, period, d, start, tm = _stats_case(oracle)
+    n = len(t)
+    st, per = oracle.transit_stats(t, y, dy, period, d, start, tm)
+    perm = oracle.fold_sort(t, period)
+    s = oracle.resample(tm, d)
+    pos = start + np.arange(d)
+    idx = perm[pos % n]
+    ep = np.floor(t[idx] / period).astype(np.int64) - (pos >= n)
+    w = 1.0 / dy[idx] ** 2
+    r = w * (1.0 - y[idx])
+    uniq = np.unique(ep)
+    assert np.array_equal(per["epoch"], uniq)
+    assert st["n_transits"] == len(uniq) and st["n_in"] == d and st["first_epoch"] == uniq[0]
+    for a, e in enumerate(uniq):
+        m = ep == e
+        assert per["count"][a] == m.sum()
+        assert per["depth"][a] == pytest.approx(np.sum(r[m] * s[m]) / np.sum(w[m] * s[m] ** 2), rel=1e-12)
+        assert per["sigma"][a] == pytest.approx(1.0 / math.sqrt(np.sum(w[m] * s[m] ** 2)), rel=1e-12)
+    # transits counted from the window's first phase group the points the same way
+    ph0 = oracle.phase(t[idx[0]], period)
+    ep2 = np.floor((t[idx] - ph0 * period) / period + 1e-9).astype(np.int64)
+    for e in uniq:
+        assert len(np.unique(ep2[ep == e])) == 1
+    c, b = np.sum(r * s), np.sum(w * s * s)
+    depth = c / b
+    assert st["depth"] == pytest.approx(depth, rel=1e-12)
+    chi2_0 = oracle.chi2_null(y, dy)
+    chi2_fit = oracle.chi2_literal(y, dy, perm, start, d, s, depth)
+    assert st["snr"] ** 2 == pytest.approx(chi2_0 - chi2_fit, rel=1e-8) if depth > 0 else st["snr"] == 0.0
+
+
+def test_transit_stats_recovers_odd_even_depths(oracle):
+    """Window points replaced by 1 - depth_e s_k with odd and even depths:
+    every per-transit depth, the odd and even pools and the mismatch follow
+    exactly."""
+    t, y, dy, period, d, start, tm = _stats_case(oracle, seed=9)
+    n = len(t)
+    perm = oracle.fold_sort(t, period)
+    s = oracle.resample(tm, d)
+    pos = start + np.arange(d)
+    idx = perm[pos % n]
+    ep = np.floor(t[idx] / period).astype(np.int64) - (pos >= n)
+    y = np.ones(n)
+    dodd, deven = 3e-3, 1e-3
+    y[idx] = 1.0 - np.where(ep % 2 == 1, dodd, deven) * s
+    st, per = oracle.transit_stats(t, y, dy, period, d, start, tm)
+    want = np.where(per["epoch"] % 2 == 1, dodd, deven)
+    assert np.allclose(per["depth"], want, rtol=1e-12, atol=0)
+    assert st["depth_odd"] == pytest.approx(dodd, rel=1e-12)
+    assert st["depth_even"] == pytest.approx(deven, rel=1e-12)
+    so, se = st["sigma_odd"], st["sigma_even"]
+    assert st["odd_even_sigma"] == pytest.approx(abs(dodd - deven) / math.sqrt(so * so + se * se), rel=1e-12)
+    # a depth shared by every transit: no mismatch, and the pooled depth is that depth
+    y[idx] = 1.0 - 2e-3 * s
+    st, _ = oracle.transit_stats(t, y, dy, period, d, start, tm)
+    assert st["depth"] == pytest.approx(2e-3, rel=1e-12)
+    assert st["odd_even_sigma"] == pytest.approx(0.0, abs=1e-9)
+
+
+def test_transit_stats_scale_invariance(oracle):
+    """dy * 2^k leaves every depth unchanged bit for bit and scales sigma by
+    2^k and the SNR (depth over its standard error) by 2^-k."""
+    t, y, dy, period, d, start, tm = _stats_case(oracle, seed=3, start=100)
+    st0, p0 = oracle.transit_stats(t, y, dy, period, d, start, tm)
+    st1, p1 = oracle.transit_stats(t, y, dy * 4.0, period, d, start, tm)
+    assert np.array_equal(p0["depth"], p1["depth"]) and np.array_equal(p0["epoch"], p1["epoch"])
+    assert np.array_equal(p0["sigma"] * 4.0, p1["sigma"])
+    assert st0["snr"] == st1["snr"] * 4.0 and st0["depth_odd"] == st1["depth_odd"]
