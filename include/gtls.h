@@ -216,6 +216,51 @@ gtls_status tls_search_batch_dev(gtls_ctx *ctx, const int64_t *offsets, const do
 gtls_status tls_fold_sort(gtls_ctx *ctx, const double *time, int64_t n,
                           const double *periods, int32_t n_periods, int32_t *perm);
 
+/* Statistics of one transit window: the SNR and the per-transit and
+ * odd/even depths that Sect. 1, 2.5 and 3 name without formulas.  The window
+ * is the search's: the duration's D points (D from the period and duration
+ * as in the search) from sorted position `start` of the curve folded at
+ * `period`, sorted position p mod n, "wrapped" when p >= n.  Window point k
+ * (input index i) belongs to the transit of epoch floor(t_i / period) - 1
+ * if wrapped, else floor(t_i / period).  Per transit, over its points in
+ * ascending k, c = sum w (1 - y) s_k and b = sum w s_k^2 (w = 1/dy^2, s the
+ * D-point template, fused multiply-adds); depth = c / b, sigma = 1/sqrt(b).
+ * Odd epochs, even epochs and all epochs pool c and b (C, B) in ascending
+ * epoch order.  Reading: SNR = max(C, 0) / sqrt(B), the pooled depth over
+ * its standard error, i.e. sqrt(chi2_0 - chi2) of the window's weighted
+ * least-squares fit; the mid-transit time of epoch e is (e + phase_mid) *
+ * period.  Values are FP64 whatever params would say. */
+typedef struct {
+    double snr;            /* max(C, 0) / sqrt(B)                                    */
+    double depth;          /* C / B, all transits (not clamped)                      */
+    double depth_odd;      /* pooled over odd epochs; NaN when there is none         */
+    double depth_even;     /* pooled over even epochs; NaN when there is none        */
+    double sigma_odd;      /* 1/sqrt(B_odd); NaN when there is none                  */
+    double sigma_even;     /* 1/sqrt(B_even); NaN when there is none                 */
+    double odd_even_sigma; /* |depth_odd - depth_even| / sqrt(sigma_odd^2 + sigma_even^2); NaN if a side is empty */
+    double phase_mid;      /* phase of the window's middle point (position start + D/2), +1 if wrapped */
+    int64_t n_in;          /* D, the window's points                                 */
+    int64_t n_transits;    /* epochs with at least one window point                  */
+    int64_t first_epoch;   /* the lowest such epoch                                  */
+} gtls_transit_stats;
+
+/* Transit statistics at one window, host arrays.
+ *   time, flux, dy [n]: the light curve (rules of tls_search);
+ *   period, duration: days, > 0 (typically period_grid[best] and
+ *     duration_grid[best_dur] of a search); start in [0, n): the window's
+ *     first sorted position (best_start of that search);
+ *   tmpl [n_tmpl]: as in tls_search;
+ *   stats: written on success and when the transits exceed max_transits;
+ *   epoch, t_mid, depth, sigma, count [max_transits] (any may be NULL when
+ *     max_transits is 0): the transits with points, ascending epoch.
+ * Returns GTLS_EINVAL (with stats filled and n_transits set) when there are
+ * more than max_transits transits.  Synchronous. */
+gtls_status tls_transit_stats(gtls_ctx *ctx, const double *time, const double *flux,
+                              const double *dy, int64_t n, double period, double duration,
+                              const double *tmpl, int32_t n_tmpl, int64_t start,
+                              gtls_transit_stats *stats, int64_t max_transits, int64_t *epoch,
+                              double *t_mid, double *depth, double *sigma, int64_t *count);
+
 /* Periodogram statistics alone (Sect. 2.4) on a host chi2 array of n > 0
  * values: sr, sde_raw, sde [n] (any may be NULL) and the first argmax of sde.
  * window must be odd and >= 1. */

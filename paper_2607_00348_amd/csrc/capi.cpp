@@ -407,6 +407,79 @@ gtls_status tls_fold_sort(gtls_ctx* ctx, const double* time, int64_t n, const do
     return GTLS_OK;
 }
 
+gtls_status tls_transit_stats(gtls_ctx* ctx, const double* time, const double* flux, const double* dy, int64_t n,
+                              double period, double duration, const double* tmpl, int32_t n_tmpl, int64_t start,
+                              gtls_transit_stats* stats, int64_t max_transits, int64_t* epoch, double* t_mid,
+                              double* depth, double* sigma, int64_t* count) {
+    if (!ctx) return GTLS_EINVAL;
+    if (!stats) return fail(ctx, GTLS_EINVAL, "null stats");
+    gtls_status st = check_sizes(ctx, n, 1, 1, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if (!(period > 0.0) || !std::isfinite(period) || !(duration > 0.0) || !std::isfinite(duration))
+        return fail(ctx, GTLS_EINVAL, "period and duration must be finite and > 0");
+    st = check_host_data(ctx, time, flux, dy, n, &period, 1, &duration, 1, tmpl, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if (start < 0 || start >= n) return fail(ctx, GTLS_EINVAL, "start must be in [0, n)");
+    if (max_transits < 0) return fail(ctx, GTLS_EINVAL, "max_transits must be >= 0");
+    if (max_transits > 0 && (!epoch || !t_mid || !depth || !sigma || !count))
+        return fail(ctx, GTLS_EINVAL, "null per-transit array");
+    // window points as in the search: D = floor(n duration / period + 1/2) in [1, n]
+    const double q = duration / period;
+    double dd = std::floor((double)n * q + 0.5);
+    const int64_t d = dd < 1.0 ? 1 : (dd > (double)n ? n : (int64_t)dd);
+    // epochs lie between floor(min t / P) - 1 and floor(max t / P)
+    double tmin = time[0], tmax = time[0];
+    for (int64_t i = 1; i < n; ++i) {
+        tmin = std::min(tmin, time[i]);
+        tmax = std::max(tmax, time[i]);
+    }
+    const double span_epochs = std::floor(tmax / period) - std::floor(tmin / period) + 2.0;
+    if (!(span_epochs < 1e8)) return fail(ctx, GTLS_EINVAL, "more than 1e8 epochs in the time span");
+    const int64_t nep_max = (int64_t)span_epochs;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    const size_t nn = (size_t)n, mt = (size_t)max_transits;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t o_t = take(8 * nn), o_y = take(8 * nn), o_dy = take(8 * nn), o_tm = take(8 * (size_t)n_tmpl),
+                 o_p = take(8), o_st = take(sizeof(gtls_transit_stats)), o_ep = take(8 * mt), o_tmid = take(8 * mt),
+                 o_dep = take(8 * mt), o_sig = take(8 * mt), o_cnt = take(8 * mt);
+    e = gtls::ensure(ctx, ctx->io, o);
+    if (e != hipSuccess) return hip_fail(ctx, e, "device buffers");
+    char* b = (char*)ctx->io.ptr;
+    hipStream_t s = ctx->stream;
+    e = hipMemcpyAsync(b + o_t, time, 8 * nn, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_y, flux, 8 * nn, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_dy, dy, 8 * nn, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_tm, tmpl, 8 * (size_t)n_tmpl, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + o_p, &period, 8, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to device");
+    e = gtls::run_transit_stats(ctx, (double*)(b + o_t), (double*)(b + o_y), (double*)(b + o_dy), n,
+                                (double*)(b + o_p), d, start, (double*)(b + o_tm), n_tmpl, nep_max, max_transits,
+                                (gtls_transit_stats*)(b + o_st), (int64_t*)(b + o_ep), (double*)(b + o_tmid),
+                                (double*)(b + o_dep), (double*)(b + o_sig), (int64_t*)(b + o_cnt));
+    if (e != hipSuccess) return hip_fail(ctx, e, "transit statistics");
+    e = hipMemcpyAsync(stats, b + o_st, sizeof(gtls_transit_stats), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    const size_t k = (size_t)std::min<int64_t>(stats->n_transits, max_transits);
+    if (k > 0) {
+        e = hipMemcpyAsync(epoch, b + o_ep, 8 * k, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(t_mid, b + o_tmid, 8 * k, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(depth, b + o_dep, 8 * k, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(sigma, b + o_sig, 8 * k, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(count, b + o_cnt, 8 * k, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "copy to host");
+    }
+    if (stats->n_transits > max_transits) return fail(ctx, GTLS_EINVAL, "more transits than max_transits");
+    return GTLS_OK;
+}
+
 gtls_status tls_sde(gtls_ctx* ctx, const double* chi2, int32_t n, int32_t window, double* sr, double* sde_raw,
                     double* sde, int32_t* best) {
     if (!ctx) return GTLS_EINVAL;

@@ -121,6 +121,10 @@ namespace gtls {
 hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a);
 hipError_t run_fold_sort(gtls_ctx* ctx, const double* t_dev, int64_t n, const double* periods_dev,
                          int32_t n_periods, int32_t* perm_dev);
+hipError_t run_transit_stats(gtls_ctx* ctx, const double* t, const double* y, const double* dy, int64_t n,
+                             const double* period_dev, int64_t d, int64_t start, const double* tm, int32_t nt,
+                             int64_t nep_max, int64_t max_transits, gtls_transit_stats* st_dev, int64_t* epoch,
+                             double* t_mid, double* depth, double* sigma, int64_t* count);
 hipError_t run_sde(gtls_ctx* ctx, const double* chi2_dev, int32_t n, int32_t window, double* sr_dev,
                    double* raw_dev, double* sde_dev, gtls_summary* summary_dev);
 hipError_t ensure(gtls_ctx* ctx, DeviceBuffer& b, size_t bytes);

@@ -2582,4 +2582,185 @@ hipError_t run_fold_sort(gtls_ctx* ctx, const double* t, int64_t n, const double
     return hipSuccess;
 }
 
+namespace {
+
+// ------------------------------------------------------------------------
+// Transit statistics at one window (SNR, per-transit and odd/even depths).
+// Window point k (padded position p = start + k, sorted position p mod n,
+// wrapped when p >= n) of input index idx belongs to the transit of epoch
+// floor(t_idx / P) - wrapped.  Per epoch, over its points in ascending k,
+// c = sum fma(r, s_k, .) and b = sum fma(w, s_k^2, .); odd, even and all
+// epochs then pool c and b in ascending epoch order.  SNR = max(C, 0) /
+// sqrt(B), the pooled depth over its standard error.
+
+// Per window point: epoch, r, w, template value; the epoch range (epochs as
+// order-preserving unsigned words: e XOR 2^63).
+__global__ __launch_bounds__(256) void k_ts_points(const double* __restrict__ t, const double* __restrict__ y,
+                                                   const double* __restrict__ dy, const int32_t* __restrict__ perm,
+                                                   int64_t n, const double* __restrict__ period_p, int64_t d,
+                                                   int64_t start, const double* __restrict__ tm, int32_t nt,
+                                                   int64_t* __restrict__ ek, double* __restrict__ rk,
+                                                   double* __restrict__ wk, double* __restrict__ sk,
+                                                   unsigned long long* erange) {
+    __shared__ unsigned long long lo[256], hi[256];
+    const int tid = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * 256 + tid;
+    const double period = *period_p;
+    unsigned long long a = ~0ull, b = 0ull;
+    if (k < d) {
+        const int64_t p = start + k;
+        const int wrapped = p >= n ? 1 : 0;
+        const int32_t idx = perm[wrapped ? p - n : p];
+        const double w = 1.0 / (dy[idx] * dy[idx]);
+        const int64_t e = (int64_t)floor(t[idx] / period) - wrapped;
+        ek[k] = e;
+        rk[k] = w * (1.0 - y[idx]);
+        wk[k] = w;
+        sk[k] = resample(tm, nt, d, k);
+        a = b = (unsigned long long)e ^ 0x8000000000000000ull;
+    }
+    lo[tid] = a;
+    hi[tid] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            lo[tid] = min(lo[tid], lo[tid + s]);
+            hi[tid] = max(hi[tid], hi[tid + s]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        atomicMin(&erange[0], lo[0]);
+        atomicMax(&erange[1], hi[0]);
+    }
+}
+
+// One thread per epoch: its points' sums in ascending k (every lane walks
+// all window points, which it reads at the same address as the rest of its
+// wave).
+__global__ __launch_bounds__(256) void k_ts_epochs(const int64_t* __restrict__ ek, const double* __restrict__ rk,
+                                                   const double* __restrict__ wk, const double* __restrict__ sk,
+                                                   int64_t d, int64_t emin, int64_t nep, double* __restrict__ ce,
+                                                   double* __restrict__ be, int64_t* __restrict__ ne) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t e = emin + j;
+    double c = 0.0, b = 0.0;
+    int64_t cnt = 0;
+    for (int64_t k = 0; k < d; ++k) {
+        if (ek[k] == e) {
+            c = fma(rk[k], sk[k], c);
+            const double s2 = sk[k] * sk[k];
+            b = fma(wk[k], s2, b);
+            ++cnt;
+        }
+    }
+    if (j < nep) {
+        ce[j] = c;
+        be[j] = b;
+        ne[j] = cnt;
+    }
+}
+
+// Pools the epochs in ascending order and writes the statistics (one thread).
+__global__ void k_ts_final(const double* __restrict__ ce, const double* __restrict__ be,
+                           const int64_t* __restrict__ ne, int64_t emin, int64_t nep, const double* __restrict__ t,
+                           const int32_t* __restrict__ perm, int64_t n, const double* __restrict__ period_p,
+                           int64_t d, int64_t start, int64_t max_transits, gtls_transit_stats* __restrict__ st,
+                           int64_t* __restrict__ epoch, double* __restrict__ t_mid, double* __restrict__ depth,
+                           double* __restrict__ sigma, int64_t* __restrict__ count) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double period = *period_p;
+    const int64_t pm = start + d / 2;
+    const double phase_mid = phase_of(t[perm[pm >= n ? pm - n : pm]], period) + (pm >= n ? 1.0 : 0.0);
+    double c_all = 0.0, b_all = 0.0, c_odd = 0.0, b_odd = 0.0, c_even = 0.0, b_even = 0.0;
+    int64_t nt = 0, first = 0;
+    for (int64_t j = 0; j < nep; ++j) {
+        if (ne[j] == 0) continue;
+        const int64_t e = emin + j;
+        if (nt == 0) first = e;
+        if (nt < max_transits) {
+            epoch[nt] = e;
+            t_mid[nt] = ((double)e + phase_mid) * period;
+            depth[nt] = ce[j] / be[j];
+            sigma[nt] = 1.0 / sqrt(be[j]);
+            count[nt] = ne[j];
+        }
+        ++nt;
+        c_all += ce[j];
+        b_all += be[j];
+        if (((e % 2) + 2) % 2 == 1) {
+            c_odd += ce[j];
+            b_odd += be[j];
+        } else {
+            c_even += ce[j];
+            b_even += be[j];
+        }
+    }
+    const double d_odd = b_odd > 0.0 ? c_odd / b_odd : NAN, s_odd = b_odd > 0.0 ? 1.0 / sqrt(b_odd) : NAN;
+    const double d_even = b_even > 0.0 ? c_even / b_even : NAN, s_even = b_even > 0.0 ? 1.0 / sqrt(b_even) : NAN;
+    st->snr = (c_all > 0.0 ? c_all : 0.0) / sqrt(b_all);
+    st->depth = c_all / b_all;
+    st->depth_odd = d_odd;
+    st->depth_even = d_even;
+    st->sigma_odd = s_odd;
+    st->sigma_even = s_even;
+    st->odd_even_sigma =
+        (b_odd > 0.0 && b_even > 0.0) ? fabs(d_odd - d_even) / sqrt(s_odd * s_odd + s_even * s_even) : NAN;
+    st->phase_mid = phase_mid;
+    st->n_in = d;
+    st->n_transits = nt;
+    st->first_epoch = first;
+}
+
+}  // namespace
+
+// Statistics of the window of d points from sorted position `start` of the
+// curve folded at *period_dev (device arrays; scratch from the context).
+hipError_t run_transit_stats(gtls_ctx* ctx, const double* t, const double* y, const double* dy, int64_t n,
+                             const double* period_dev, int64_t d, int64_t start, const double* tm, int32_t nt,
+                             int64_t nep_max, int64_t max_transits, gtls_transit_stats* st_dev, int64_t* epoch,
+                             double* t_mid, double* depth, double* sigma, int64_t* count) {
+    hipStream_t s = ctx->stream;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t o_perm = take(4 * (size_t)n), o_ek = take(8 * (size_t)d), o_rk = take(8 * (size_t)d),
+                 o_wk = take(8 * (size_t)d), o_sk = take(8 * (size_t)d), o_er = take(16),
+                 o_ce = take(8 * (size_t)nep_max), o_be = take(8 * (size_t)nep_max), o_ne = take(8 * (size_t)nep_max);
+    hipError_t e = ensure(ctx, ctx->sde_tmp, o);
+    if (e != hipSuccess) return e;
+    char* b = (char*)ctx->sde_tmp.ptr;
+    int32_t* perm = (int32_t*)(b + o_perm);
+    e = run_fold_sort(ctx, t, n, period_dev, 1, perm);
+    if (e != hipSuccess) return e;
+    unsigned long long* er = (unsigned long long*)(b + o_er);
+    k_fill_u64<<<1, 256, 0, s>>>(er, 1, ~0ull);
+    k_fill_u64<<<1, 256, 0, s>>>(er + 1, 1, 0ull);
+    k_ts_points<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(t, y, dy, perm, n, period_dev, d, start, tm, nt,
+                                                            (int64_t*)(b + o_ek), (double*)(b + o_rk),
+                                                            (double*)(b + o_wk), (double*)(b + o_sk), er);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    unsigned long long range[2];
+    e = hipMemcpyAsync(range, er, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    const int64_t emin = (int64_t)(range[0] ^ 0x8000000000000000ull), emax = (int64_t)(range[1] ^ 0x8000000000000000ull);
+    const int64_t nep = emax - emin + 1;
+    if (nep < 1 || nep > nep_max) return hipErrorInvalidValue;   // cannot happen: epochs lie in the time span
+    k_ts_epochs<<<(unsigned)((nep + 255) / 256), 256, 0, s>>>((const int64_t*)(b + o_ek), (const double*)(b + o_rk),
+                                                              (const double*)(b + o_wk), (const double*)(b + o_sk),
+                                                              d, emin, nep, (double*)(b + o_ce), (double*)(b + o_be),
+                                                              (int64_t*)(b + o_ne));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ts_final<<<1, 64, 0, s>>>((const double*)(b + o_ce), (const double*)(b + o_be), (const int64_t*)(b + o_ne),
+                                emin, nep, t, perm, n, period_dev, d, start, max_transits, st_dev, epoch, t_mid,
+                                depth, sigma, count);
+    return hipGetLastError();
+}
+
 }  // namespace gtls

@@ -24,7 +24,7 @@ GTLS_DEPTH_WLS, GTLS_DEPTH_MEAN = 0, 1
 EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_default", "gtls_sync",
             "gtls_profile_enable", "gtls_profile_read",
             "tls_search", "tls_search_dev", "tls_search_batch", "tls_search_batch_dev", "tls_fold_sort",
-            "tls_sde", "tls_search_refined", "gtls_period_grid_ofir",
+            "tls_sde", "tls_search_refined", "tls_transit_stats", "gtls_period_grid_ofir",
             "gtls_duration_grid", "gtls_template_quadratic", "gtls_cnn_num_params", "gtls_cnn_create",
             "gtls_cnn_destroy", "gtls_cnn_view", "gtls_cnn_forward", "gtls_cnn_gradients", "gtls_cnn_train_step",
             "gtls_cnn_get_params", "gtls_cnn_topk"]
@@ -51,6 +51,13 @@ class gtls_result(ctypes.Structure):
 class gtls_summary(ctypes.Structure):
     _fields_ = [("chi2_null", ctypes.c_double), ("sde_max", ctypes.c_double), ("n_evals", ctypes.c_int64),
                 ("n_macs", ctypes.c_int64), ("best_period", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class gtls_transit_stats(ctypes.Structure):
+    _fields_ = [("snr", ctypes.c_double), ("depth", ctypes.c_double), ("depth_odd", ctypes.c_double),
+                ("depth_even", ctypes.c_double), ("sigma_odd", ctypes.c_double), ("sigma_even", ctypes.c_double),
+                ("odd_even_sigma", ctypes.c_double), ("phase_mid", ctypes.c_double), ("n_in", ctypes.c_int64),
+                ("n_transits", ctypes.c_int64), ("first_epoch", ctypes.c_int64)]
 
 
 STAGES = ("prep", "fold_sort", "slide", "reduce", "sde", "slide_strided")
@@ -108,6 +115,11 @@ def lib():
                                            vp, vp]
         L.tls_fold_sort.restype = ctypes.c_int
         L.tls_fold_sort.argtypes = [vp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _ip]
+        _lp = ctypes.POINTER(ctypes.c_int64)
+        L.tls_transit_stats.restype = ctypes.c_int
+        L.tls_transit_stats.argtypes = [vp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _dp,
+                                        ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(gtls_transit_stats),
+                                        ctypes.c_int64, _lp, _dp, _dp, _dp, _lp]
         L.tls_sde.restype = ctypes.c_int
         L.tls_sde.argtypes = [vp, _dp, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _ip]
         L.tls_search_refined.restype = ctypes.c_int
@@ -341,6 +353,25 @@ def tls_fold_sort(ctx: Context, time, periods) -> np.ndarray:
     perm = np.empty((len(per), len(t)), dtype=np.int32)
     _check(lib().tls_fold_sort(ctx.ptr, _p(t), len(t), _p(per), len(per), perm.ctypes.data_as(_ip)), ctx.ptr)
     return perm
+
+
+def tls_transit_stats(ctx: Context, time, flux, dy, period: float, duration: float, tmpl, start: int,
+                      max_transits: int = 65536):
+    """SNR, per-transit and odd/even depths of the window of the search's
+    best (period, duration, start); see include/gtls.h.  Returns (stats
+    dict, per-transit dict of arrays: epoch, t_mid, depth, sigma, count)."""
+    t, y, e, tm = _f64(time), _f64(flux), _f64(dy), _f64(tmpl)
+    st = gtls_transit_stats()
+    cap = int(max_transits)
+    ep, cn = np.zeros(cap, dtype=np.int64), np.zeros(cap, dtype=np.int64)
+    tmid, dep, sig = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    lp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    _check(lib().tls_transit_stats(ctx.ptr, _p(t), _p(y), _p(e), len(t), float(period), float(duration), _p(tm),
+                                   len(tm), int(start), ctypes.byref(st), cap, lp(ep), _p(tmid), _p(dep), _p(sig),
+                                   lp(cn)), ctx.ptr)
+    stats = {f: getattr(st, f) for f, _ in gtls_transit_stats._fields_}
+    k = int(st.n_transits)
+    return stats, {"epoch": ep[:k], "t_mid": tmid[:k], "depth": dep[:k], "sigma": sig[:k], "count": cn[:k]}
 
 
 def tls_sde(ctx: Context, chi2, window: int = 91):
