@@ -234,8 +234,13 @@ __device__ __forceinline__ bool key_less(uint64_t a, uint64_t b, const double* _
     return (uint32_t)a < (uint32_t)b;
 }
 
+constexpr int kTieCap = 2048;   // equal-key neighbours listed during the last pass
+
 template <int NT>
 struct SortShared {
+    uint32_t lastkey[256];       // last pass: key of the last word written per digit (0xffffffff: none yet)
+    uint32_t tie_n;              // last pass: output positions whose key equals the previous position's
+    uint32_t tie_pos[kTieCap];
     uint32_t hist[3][256];
     uint32_t wcnt[NT / 64][256];
     uint32_t dbase[256];
@@ -325,6 +330,8 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
     const int lane = tid & 63;
     for (int k = tid; k < 3 * 256; k += NT) (&sh.hist[0][0])[k] = 0;
     for (int k = tid; k < W * 256; k += NT) (&sh.wcnt[0][0])[k] = 0;
+    for (int k = tid; k < 256; k += NT) sh.lastkey[k] = 0xffffffffu;   // keys are < 2^24
+    if (tid == 0) sh.tie_n = 0;
     __syncthreads();
     for (int64_t i = tid; i < n; i += NT) {
         const uint32_t key = phase_key(phase_of(t[i], period));
@@ -442,11 +449,26 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
                 const uint32_t pos = sh.dbase[d] + (uint32_t)i - sh.tstart[d];
                 if (pos < (uint32_t)n) {
                     dst[pos] = it;
-                    if (pass == 2 && gather) pad_store(po, n, pos, (uint32_t)it);
+                    if (pass == 2) {
+                        if (gather) pad_store(po, n, pos, (uint32_t)it);
+                        // the word before it in the output: the previous one of its digit's run in this
+                        // tile, or the last one an earlier tile wrote for the digit
+                        const uint32_t key = (uint32_t)(it >> 32);
+                        const uint32_t prev = (uint32_t)i > sh.tstart[d] ? (uint32_t)(sh.buf[i - 1] >> 32)
+                                                                         : sh.lastkey[d];
+                        if (key == prev) {
+                            const uint32_t slot = atomicAdd(&sh.tie_n, 1u);
+                            if (slot < (uint32_t)kTieCap) sh.tie_pos[slot] = pos;
+                        }
+                    }
                 }
             }
             __syncthreads();
-            if (tid < 256) sh.dbase[tid] += sh.tcount[tid];
+            if (tid < 256) {
+                sh.dbase[tid] += sh.tcount[tid];
+                if (pass == 2 && sh.tcount[tid] > 0)
+                    sh.lastkey[tid] = (uint32_t)(sh.buf[sh.tstart[tid] + sh.tcount[tid] - 1] >> 32);
+            }
             for (int k = tid; k < W * 256; k += NT) (&sh.wcnt[0][0])[k] = 0;
             __syncthreads();
             if constexpr (PREFETCH) {
@@ -458,33 +480,48 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
     // A: order by 24-bit key, equal keys in input order.  Equal keys may hide
     // different phases: order each run by the full FP64 phase, then input
     // index (insertion sort; runs are short), and rewrite its padded copies.
-    // Each thread checks 8 consecutive positions per trip, their 10 keys
-    // (positions k0 - 1 .. k0 + 8; none outside [0, n)) loaded at once.
-    for (int64_t k0 = (int64_t)tid * 8; k0 + 1 < n; k0 += (int64_t)NT * 8) {
-        uint32_t kv[10];
-#pragma unroll
-        for (int q = 0; q < 10; ++q) {
-            const int64_t p = k0 - 1 + q;
-            kv[q] = (p >= 0 && p < n) ? (uint32_t)(A[p] >> 32) : 0xffffffffu;   // keys are < 2^24
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t k = k0 + j;
-            const uint32_t kk = kv[j + 1];
-            if (k + 1 >= n || kk != kv[j + 2] || kv[j] == kk) continue;
-            int64_t e = k + 1;
-            while (e + 1 < n && (uint32_t)(A[e + 1] >> 32) == kk) ++e;
-            for (int64_t x = k + 1; x <= e; ++x) {
-                const uint64_t v = A[x];
-                int64_t y = x;
-                while (y > k && key_less(v, A[y - 1], t, period)) {
-                    A[y] = A[y - 1];
-                    --y;
-                }
-                A[y] = v;
+    // The last pass listed every position whose key equals its predecessor's;
+    // a run is fixed by the thread holding its first pair.  When the list
+    // overflowed, every position is checked instead (8 consecutive positions
+    // per thread and trip, their 10 keys loaded at once).
+    auto fix_run = [&](int64_t k, uint32_t kk) {
+        int64_t e = k + 1;
+        while (e + 1 < n && (uint32_t)(A[e + 1] >> 32) == kk) ++e;
+        for (int64_t x = k + 1; x <= e; ++x) {
+            const uint64_t v = A[x];
+            int64_t y = x;
+            while (y > k && key_less(v, A[y - 1], t, period)) {
+                A[y] = A[y - 1];
+                --y;
             }
-            if (gather)
-                for (int64_t x = k; x <= e; ++x) pad_store(po, n, x, (uint32_t)A[x]);
+            A[y] = v;
+        }
+        if (gather)
+            for (int64_t x = k; x <= e; ++x) pad_store(po, n, x, (uint32_t)A[x]);
+    };
+    const uint32_t nties = sh.tie_n;
+    if (nties <= (uint32_t)kTieCap) {
+        for (uint32_t q = tid; q < nties; q += NT) {
+            const int64_t k = (int64_t)sh.tie_pos[q] - 1;
+            const uint32_t kk = (uint32_t)(A[k] >> 32);
+            if (k > 0 && (uint32_t)(A[k - 1] >> 32) == kk) continue;   // not its run's first pair
+            fix_run(k, kk);
+        }
+    } else {
+        for (int64_t k0 = (int64_t)tid * 8; k0 + 1 < n; k0 += (int64_t)NT * 8) {
+            uint32_t kv[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                const int64_t p = k0 - 1 + q;
+                kv[q] = (p >= 0 && p < n) ? (uint32_t)(A[p] >> 32) : 0xffffffffu;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t k = k0 + j;
+                const uint32_t kk = kv[j + 1];
+                if (k + 1 >= n || kk != kv[j + 2] || kv[j] == kk) continue;
+                fix_run(k, kk);
+            }
         }
     }
     __syncthreads();
