@@ -1130,11 +1130,18 @@ __device__ __forceinline__ void unrolled(F&& f) {
     unrolled_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
-// The 16 template steps of one chunk in ascending order.
-template <typename T, int R, int... U>
-__device__ __forceinline__ void dpp_chunk(T (&acc)[R], const T (&tv)[R], const T (&x)[kSC],
-                                          std::integer_sequence<int, U...>) {
-    (dpp_fmac<U>(acc, tv, x[U]), ...);
+// The 16 template steps of one chunk in ascending order.  The template
+// block covers two chunks, two points per lane: point j of chunk H sits in
+// lane 8 H + j / 2 of every row, in tlo for even j and thi for odd j.
+template <typename T, int R, int H, int J>
+__device__ __forceinline__ void dpp_step(T (&acc)[R], const T (&tlo)[R], const T (&thi)[R], const T (&x)[kSC]) {
+    if constexpr (J % 2 == 0) dpp_fmac<8 * H + J / 2>(acc, tlo, x[J]);
+    else dpp_fmac<8 * H + J / 2>(acc, thi, x[J]);
+}
+template <typename T, int R, int H, int... J>
+__device__ __forceinline__ void dpp_chunk(T (&acc)[R], const T (&tlo)[R], const T (&thi)[R], const T (&x)[kSC],
+                                          std::integer_sequence<int, J...>) {
+    (dpp_step<T, R, H, J>(acc, tlo, thi, x), ...);
 }
 
 // Loads sizeof(V) bytes at a 32-bit byte offset from a wave-uniform base
@@ -1159,19 +1166,24 @@ __device__ Best strided_windows_coop(const SlideItem& si, int64_t m_lo, int64_t 
     const T* __restrict__ tbase = (const T*)si.trow - 2 * kSC;   // the row's 32 leading zeros
     const int64_t J = D + (R - 1) * s;              // points of a lane's run
     const int64_t nch = (J + kSC - 1) / kSC;
-    const uint32_t tl = (uint32_t)(lane & 15) * sizeof(T);
+    const uint32_t tl = (uint32_t)(lane & 15) * 2 * sizeof(T);
     T* const srow = stage + lane * kStRow<T>;
     T* const srow_w = VARW ? stage_w + lane * kStRow<T> : nullptr;
 
-    // Template block of window r at chunk c0: lane l holds point c0 - r s + l mod 16.
-    // Blocks wholly before the row read 16 of its 32 leading zeros, blocks at
-    // or past its end the zeros that follow it, so no branch is needed.
-    auto tload = [&](int64_t c0, T (&tv)[R]) {
+    // Template block of window r for the two chunks from c0: lane l holds
+    // points c0 - r s + 2 (l mod 16) and the next (one load per window per
+    // two chunks).  Blocks wholly before the row read its 32 leading zeros,
+    // blocks at or past its end the zeros that follow it, so no branch is
+    // needed.
+    struct TPair {
+        T lo, hi;
+    };
+    auto tload = [&](int64_t c0, TPair (&tv)[R]) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t klo = c0 - (int64_t)r * s;
-            const int64_t kc = klo <= -kSC ? -2 * kSC : (klo >= D ? D : klo);
-            tv[r] = load_at<T>(tbase, (uint32_t)(kc + 2 * kSC) * (uint32_t)sizeof(T) + tl);
+            const int64_t kc = klo <= -2 * kSC ? -2 * kSC : (klo >= D ? D : klo);
+            tv[r] = load_at<TPair>(tbase, (uint32_t)(kc + 2 * kSC) * (uint32_t)sizeof(T) + tl);
         }
     };
     auto stage_get = [&](const T* row, T (&x)[kSC]) {
@@ -1182,22 +1194,29 @@ __device__ Best strided_windows_coop(const SlideItem& si, int64_t m_lo, int64_t 
             for (int e = 0; e < P; ++e) x[i * P + e] = pc.v[e];
         }
     };
-    auto products = [&](double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
-                        const T (&xw)[VARW ? kSC : 1], const T (&tv)[R]) {
-        T tq[VARW ? R : 1];
-        if constexpr (VARW) {
+    // products of chunk H (0: the first of the template block's two chunks)
+    auto products = [&](auto hc, double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
+                        const T (&xw)[VARW ? kSC : 1], const TPair (&tv)[R]) {
+        constexpr int H = decltype(hc)::value;
+        T tlo[R], thi[R], qlo[VARW ? R : 1], qhi[VARW ? R : 1];
 #pragma unroll
-            for (int r = 0; r < R; ++r) tq[r] = tv[r] * tv[r];
+        for (int r = 0; r < R; ++r) {
+            tlo[r] = tv[r].lo;
+            thi[r] = tv[r].hi;
+            if constexpr (VARW) {
+                qlo[r] = tv[r].lo * tv[r].lo;
+                qhi[r] = tv[r].hi * tv[r].hi;
+            }
         }
         if constexpr (sizeof(T) == 8) {
-            dpp_chunk<T, R>(acc, tv, x, std::make_integer_sequence<int, kSC>{});
-            if constexpr (VARW) dpp_chunk<T, R>(bacc, tq, xw, std::make_integer_sequence<int, kSC>{});
+            dpp_chunk<T, R, H>(acc, tlo, thi, x, std::make_integer_sequence<int, kSC>{});
+            if constexpr (VARW) dpp_chunk<T, R, H>(bacc, qlo, qhi, xw, std::make_integer_sequence<int, kSC>{});
         } else {
             T ca[R], cq[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) ca[r] = cq[r] = (T)0;
-            dpp_chunk<T, R>(ca, tv, x, std::make_integer_sequence<int, kSC>{});
-            if constexpr (VARW) dpp_chunk<T, R>(cq, tq, xw, std::make_integer_sequence<int, kSC>{});
+            dpp_chunk<T, R, H>(ca, tlo, thi, x, std::make_integer_sequence<int, kSC>{});
+            if constexpr (VARW) dpp_chunk<T, R, H>(cq, qlo, qhi, xw, std::make_integer_sequence<int, kSC>{});
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 acc[r] += (double)ca[r];
@@ -1245,14 +1264,17 @@ __device__ Best strided_windows_coop(const SlideItem& si, int64_t m_lo, int64_t 
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
 #pragma unroll
         for (int r = 0; r < (VARW ? R : 1); ++r) bacc[r] = 0.0;
-        // Chunk j's curve pieces are requested while chunk j - 2 is being
-        // computed, written to LDS and read back into the other half of x
-        // while chunk j - 1 is computed, and its template blocks are
-        // requested right after chunk j - 2's products; so the products of
-        // chunk j never wait on a load.  Two chunks per trip keep the
-        // halves' indices constant.  Chunks past the run are requested too
-        // (from clamped addresses), so every register is written every trip.
-        T x[2][kSC], xw[2][VARW ? kSC : 1], tv[2][R];
+        // Chunks go two by two (j even), one template block per window for
+        // both.  Chunk j's curve pieces are requested while chunk j - 2 is
+        // being computed, written to LDS and read back into the other half of
+        // x while chunk j - 1 is computed; the block for chunks j and j + 1 is
+        // requested right after the products of chunks j - 4 and j - 3.  So
+        // no product waits on a load.  Two pairs per trip keep the template
+        // slot indices constant.  Chunks past the run (at most one) are
+        // computed too, on clamped addresses and template zeros, so every
+        // register is written every trip.
+        T x[2][kSC], xw[2][VARW ? kSC : 1];
+        TPair tv[2][R];
         Piece<T> nx[NP], nw[VARW ? NP : 1];
         auto pieces = [&](int64_t j) {
             xload(rp, j * kSC, nx);
@@ -1260,22 +1282,26 @@ __device__ Best strided_windows_coop(const SlideItem& si, int64_t m_lo, int64_t 
         };
         pieces(0);
         tload(0, tv[0]);
-        tload(kSC, tv[1]);
+        tload(2 * kSC, tv[1]);
         restage(nx, nw, x[0], xw[0]);
         pieces(1);
-        auto step = [&](auto kc, int64_t j) {
-            constexpr int k = decltype(kc)::value;
-            restage(nx, nw, x[k ^ 1], xw[k ^ 1]);
+        auto pair = [&](auto slotc, int64_t j) {
+            constexpr int sl = decltype(slotc)::value;
+            restage(nx, nw, x[1], xw[1]);
             pieces(j + 2);
-            products(acc, bacc, x[k], xw[k], tv[k]);
-            tload((j + 2) * kSC, tv[k]);
+            products(std::integral_constant<int, 0>{}, acc, bacc, x[0], xw[0], tv[sl]);
+            restage(nx, nw, x[0], xw[0]);
+            pieces(j + 3);
+            products(std::integral_constant<int, 1>{}, acc, bacc, x[1], xw[1], tv[sl]);
+            tload((j + 4) * kSC, tv[sl]);
         };
+        const int64_t npair = (nch + 1) / 2;
         int64_t c = 0;
-        for (; c + 2 <= nch; c += 2) {
-            step(std::integral_constant<int, 0>{}, c);
-            step(std::integral_constant<int, 1>{}, c + 1);
+        for (; c + 2 <= npair; c += 2) {
+            pair(std::integral_constant<int, 0>{}, 2 * c);
+            pair(std::integral_constant<int, 1>{}, 2 * c + 2);
         }
-        if (c < nch) step(std::integral_constant<int, 0>{}, c);
+        if (c < npair) pair(std::integral_constant<int, 0>{}, 2 * c);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t m = ml + r;
