@@ -19,6 +19,8 @@ Workloads (Kepler long cadence = 29.4 min):
   (BJD-scale times), a 1-day gap every 13.7 d, 500 ppm white noise, a grazing
   transit (b = 0.9, P = 0.7 d, 300 ppm).
 * ``curve_random`` -- a generic curve with seeded length/noise/transit.
+* ``injection_curve`` -- a 4-year, 30-min, 110 ppm white-noise set, half of
+  it with one injected transit of P < 14 d (injection-recovery tests).
 
 Flux is produced in FP64, rounded to FP32 (the instruments' precision), and
 returned as FP64 holding FP32 values.
@@ -250,6 +252,37 @@ def survey_curve(index: int, n_curves: int = 4096, seed: int = 2, n_min: int = 4
         y = y - transit_deficit(t, **tr)
     y = y + sigma * g.standard_normal(n)
     return _curve(t, _to_fp32_flux(y), np.full(n, sigma), transit=tr, sigma=sigma, name=f"survey_{index}")
+
+
+def injection_curve(index: int, n_curves: int, seed: int = 7, days: float = 1461.0, cadence_min: float = 30.0,
+                    sigma: float = 110e-6, pos_frac: float = 0.5, pmin: float = 0.5, pmax: float = 14.0,
+                    p_min: float = 0.003, p_max: float = 0.012) -> dict:
+    """Curve `index` of an injection-recovery set (the white-noise detection
+    test of Sect. 3.1): `days` of `cadence_min` sampling from t = 0, white
+    noise `sigma` (dy = sigma).  The first pos_frac of a seeded permutation
+    of the n_curves are positives: one central (b = 0) limb-darkened transit
+    with P log-uniform in [pmin, pmax] d, radius ratio log-uniform in
+    [p_min, p_max] (central depth about 10-170 ppm), u1 ~ U(0.2, 0.6),
+    u2 ~ U(0.1, 0.4), T14 of a circular orbit around a Sun-like star and
+    T0 ~ U(0, P).  The rest are noise only."""
+    perm = rng(seed).permutation(n_curves)
+    positives = set(perm[: int(round(pos_frac * n_curves))].tolist())
+    g = rng(seed * 1_000_003 + index + 1)
+    cad = cadence_min / 1440.0
+    n = int(math.floor(days / cad))
+    t = np.arange(n, dtype=np.float64) * cad
+    y = np.ones(n)
+    tr = None
+    if index in positives:
+        period = float(math.exp(g.uniform(math.log(pmin), math.log(pmax))))
+        p = float(math.exp(g.uniform(math.log(p_min), math.log(p_max))))
+        u1, u2 = float(g.uniform(0.2, 0.6)), float(g.uniform(0.1, 0.4))
+        depth = p * p / (1.0 - u1 / 3.0 - u2 / 6.0)
+        tr = dict(period=period, t0=float(g.uniform(0.0, period)), t14=grazing_t14(period, 0.0, p), depth=depth,
+                  u1=u1, u2=u2, b=0.0)
+        y = y - transit_deficit(t, **tr)
+    y = y + sigma * g.standard_normal(n)
+    return _curve(t, _to_fp32_flux(y), np.full(n, sigma), transit=tr, sigma=sigma, name=f"injection_{index}")
 
 
 def cnn_init(seed: int = 0) -> np.ndarray:
