@@ -164,7 +164,9 @@ gtls_status tls_search(gtls_ctx *ctx, const double *time, const double *flux,
  * outputs (chi2, best_dur, best_start, depth, t0, sde_raw, sde) are device
  * arrays of n_periods and must all be non-NULL (sr may be NULL); summary is a
  * device pointer.  Validation reads only sizes and params (device data is not
- * inspected); invalid device data gives unspecified results. */
+ * inspected); invalid device data gives unspecified results.  The call waits
+ * once for the stream, after the per-curve preparation (whether the weights
+ * are constant picks the kernels), then enqueues the rest and returns. */
 gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux,
                            const double *dy, int64_t n, const double *period_grid,
                            int32_t n_periods, const double *duration_grid,
@@ -173,8 +175,10 @@ gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux
                            int32_t *best_start, double *depth, double *t0, double *sr,
                            double *sde_raw, double *sde, gtls_summary *summary);
 
-/* Batched survey: many light curves searched in one persistent launch over
- * (curve, period) work items (Sect. 2.3-2.4 per curve).
+/* Batched survey: many light curves searched in one call (Sect. 2.3-2.4 per
+ * curve).  Curves shorter than 6000 points share one persistent launch over
+ * (curve, period) work items; longer curves are searched one after the
+ * other by the single-curve kernels (faster for them; identical results).
  *   offsets [n_curves + 1], host: curve c owns points
  *     [offsets[c], offsets[c + 1]) of time/flux/dy; offsets[0] = 0, each
  *     curve has 3 <= n_c <= 2^27 points (same rules as tls_search).
@@ -200,7 +204,8 @@ gtls_status tls_search_batch(gtls_ctx *ctx, const int64_t *offsets, const double
  * best_dur, best_start, depth, t0, sr, sde_raw, sde, summaries) must be
  * non-NULL.  The kernels after the per-curve preparation run as one captured
  * HIP graph that is replayed while the arguments stay the same.  Returns
- * after enqueueing (call gtls_sync). */
+ * after enqueueing (call gtls_sync); each curve of 6000 points or more waits
+ * once for the stream, as tls_search_dev does. */
 gtls_status tls_search_batch_dev(gtls_ctx *ctx, const int64_t *offsets, const double *time,
                                  const double *flux, const double *dy, int32_t n_curves,
                                  const int64_t *period_offsets, const double *periods,

@@ -1,8 +1,10 @@
-"""GPU tests of the batched survey path (one persistent launch over many
-curves): every curve's results must equal, bit for bit, the single-curve
-search of that curve (itself bit-exact against the oracle), including ragged
-lengths, per-point errors, strided T0 grids, the moving-average depth and the
-FP32C mode; the captured graph must give the same results on every replay."""
+"""GPU tests of the batched survey path (curves under 6000 points share one
+persistent launch, longer ones go through the single-curve kernels): every
+curve's results must equal, bit for bit, the single-curve search of that
+curve (itself bit-exact against the oracle), including ragged lengths,
+per-point errors, strided T0 grids, the moving-average depth and the FP32C
+mode; mixed batches of short and long curves match the oracle; the captured
+graph must give the same results on every replay."""
 import os
 
 import numpy as np
@@ -97,6 +99,33 @@ def test_batch_matches_oracle(ctx, oracle):
         assert np.array_equal(res.best_dur[sl], ref.best_dur)
         assert np.array_equal(res.best_start[sl], ref.best_start)
         assert res.summaries[k]["best_period"] == oracle.sde(ref.chi2)[3]
+
+
+@pytest.mark.parametrize("dt0", [0.0, 0.1])
+def test_mixed_batch_matches_oracle(ctx, oracle, dt0):
+    """Short curves (persistent launch) and long ones (single-curve kernels)
+    in one call, interleaved, against the oracle curve by curve."""
+    lengths = [700, 7000, 1500, 6000, 5999, 9000]
+    curves = [synth.curve_random(900 + k, n=n, inject=(k % 2 == 0)) for k, n in enumerate(lengths)]
+    packed = _pack(oracle, curves, nper=40)
+    durs = oracle.duration_grid(0.5, 100.0, 10)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 128)
+    offs, t, y, dy, poffs, periods, grids = packed
+    print("mixed batch vs oracle", lengths, dt0, flush=True)
+    prm = gtls.gtls_params_default(dt0=dt0)
+    res = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
+    for k, c in enumerate(curves):
+        ref = oracle.tls_search(c["t"], c["y"], c["dy"], grids[k], durs, tm, dt0=dt0, threads=THREADS)
+        sl = slice(poffs[k], poffs[k + 1])
+        label = f"curve {k} n={len(c['t'])}"
+        assert np.allclose(res.chi2[sl], ref.chi2, rtol=1e-9, atol=0), label
+        assert np.array_equal(res.best_dur[sl], ref.best_dur), label
+        assert np.array_equal(res.best_start[sl], ref.best_start), label
+        _, _, sde, best = oracle.sde(ref.chi2)
+        assert np.allclose(res.sde[sl], sde, rtol=1e-9, atol=1e-12), label
+        assert res.summaries[k]["best_period"] == best and res.summaries[k]["n_evals"] == ref.n_evals, label
+    again = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
+    assert np.array_equal(again.chi2, res.chi2) and np.array_equal(again.sde, res.sde)
 
 
 def test_batch_graph_replays_on_device_buffers(ctx, oracle):
