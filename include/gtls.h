@@ -62,6 +62,11 @@ typedef struct {
     int32_t depth_mode;    /* GTLS_DEPTH_WLS (default) or GTLS_DEPTH_MEAN      */
     int32_t precision;     /* GTLS_FP64 (default) or GTLS_FP32C                */
     int32_t median_window; /* odd running-median width of the SDE detrend, 91 */
+    int32_t batch_route_min; /* batched calls only: curves of at least this many
+                              points are searched one after the other by the
+                              single-curve kernels instead of the persistent
+                              launch (identical results); 0 (default): every
+                              curve in the persistent launch                  */
 } gtls_params;
 
 /* Per-period outputs (arrays of n_periods, caller-owned) and summaries.
@@ -175,10 +180,11 @@ gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux
                            int32_t *best_start, double *depth, double *t0, double *sr,
                            double *sde_raw, double *sde, gtls_summary *summary);
 
-/* Batched survey: many light curves searched in one call (Sect. 2.3-2.4 per
- * curve).  Curves shorter than 6000 points share one persistent launch over
- * (curve, period) work items; longer curves are searched one after the
- * other by the single-curve kernels (faster for them; identical results).
+/* Batched survey: many light curves searched in one persistent launch over
+ * (curve, period) work items (Sect. 2.3-2.4 per curve); with
+ * params->batch_route_min > 0, curves of at least that many points are
+ * searched one after the other by the single-curve kernels instead (faster
+ * for long curves; identical results).
  *   offsets [n_curves + 1], host: curve c owns points
  *     [offsets[c], offsets[c + 1]) of time/flux/dy; offsets[0] = 0, each
  *     curve has 3 <= n_c <= 2^27 points (same rules as tls_search).
@@ -204,8 +210,9 @@ gtls_status tls_search_batch(gtls_ctx *ctx, const int64_t *offsets, const double
  * best_dur, best_start, depth, t0, sr, sde_raw, sde, summaries) must be
  * non-NULL.  The kernels after the per-curve preparation run as one captured
  * HIP graph that is replayed while the arguments stay the same.  Returns
- * after enqueueing (call gtls_sync); each curve of 6000 points or more waits
- * once for the stream, as tls_search_dev does. */
+ * after enqueueing (call gtls_sync); each curve routed to the single-curve
+ * kernels (batch_route_min) waits once for the stream, as tls_search_dev
+ * does. */
 gtls_status tls_search_batch_dev(gtls_ctx *ctx, const int64_t *offsets, const double *time,
                                  const double *flux, const double *dy, int32_t n_curves,
                                  const int64_t *period_offsets, const double *periods,

@@ -38,6 +38,7 @@ gtls_status check_params(gtls_ctx* ctx, const gtls_params& p) {
     if (p.precision != GTLS_FP64 && p.precision != GTLS_FP32C) return fail(ctx, GTLS_EINVAL, "unknown precision");
     if (p.median_window < 1 || p.median_window > 1023 || (p.median_window % 2) == 0)
         return fail(ctx, GTLS_EINVAL, "median_window must be odd and in [1, 1023]");
+    if (p.batch_route_min < 0) return fail(ctx, GTLS_EINVAL, "batch_route_min must be >= 0");
     return GTLS_OK;
 }
 
@@ -92,6 +93,7 @@ void gtls_params_default(gtls_params* p) {
     p->depth_mode = GTLS_DEPTH_WLS;
     p->precision = GTLS_FP64;
     p->median_window = 91;
+    p->batch_route_min = 0;
 }
 
 gtls_status gtls_create(gtls_ctx** out, int device, void* hip_stream) {

@@ -1866,12 +1866,6 @@ __global__ __launch_bounds__(256) void k_sde_argmax_batch(const int64_t* __restr
 // best) in workgroup-private scratch.
 
 constexpr int kBatchThreads = 256;
-// Curves of at least this many points are searched one at a time by the
-// single-curve kernels instead (bit-identical results).  Measured on MI355X
-// with 64 curves of n points (Kepler cadence, 20 durations, T0 step 0.1): the
-// persistent launch is 1.19x faster at n = 4409, the single-curve kernels
-// 1.03x at 6000, 1.14x at 8000 and about 2x above 70k points.
-constexpr int64_t kBatchRouteMin = 6000;
 constexpr int kMaxBatchDurations = 64;
 
 struct BatchArgs {
@@ -2461,14 +2455,14 @@ static hipError_t run_search_batch_queued(gtls_ctx* ctx, const BatchArgsHost& h,
 
 hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& h) {
     const int nc = h.nc;
-    // Host planning: curves of at least kBatchRouteMin points go through the
-    // single-curve pipeline (after the persistent launch); the others are
-    // queued for it, longest first.
+    // Host planning: with batch_route_min > 0, curves of at least that many
+    // points go through the single-curve pipeline (after the persistent
+    // launch); the others are queued for it, longest first.
     int64_t n_max = 0, dcap = 1;
     std::vector<int32_t> order, routed;
     for (int c = 0; c < nc; ++c) {
         const int64_t n = h.offsets[c + 1] - h.offsets[c];
-        if (n >= kBatchRouteMin) {
+        if (h.prm.batch_route_min > 0 && n >= h.prm.batch_route_min) {
             routed.push_back(c);
             continue;
         }
@@ -2490,8 +2484,7 @@ hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& h) {
     return e;
 }
 
-// The persistent launch over the queued curves (all shorter than
-// kBatchRouteMin).  The per-curve preparation and the periodogram kernels
+// The persistent launch over the queued curves.  The per-curve preparation and the periodogram kernels
 // run over every curve of the batch; the routed curves' outputs are
 // rewritten afterwards by their own searches.
 static hipError_t run_search_batch_queued(gtls_ctx* ctx, const BatchArgsHost& h, std::vector<int32_t>& order,
@@ -2621,6 +2614,7 @@ static hipError_t run_search_batch_queued(gtls_ctx* ctx, const BatchArgsHost& h,
                           (const void*)sb, (const void*)ctx->table.ptr})
         key.push_back((uint64_t)(uintptr_t)p);
     key.push_back((uint64_t)nc);
+    key.push_back((uint64_t)nq);
     key.push_back((uint64_t)total_items);
     key.push_back((uint64_t)grid);
     key.push_back((uint64_t)h.prm.median_window);

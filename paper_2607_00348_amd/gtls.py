@@ -34,7 +34,8 @@ CNN_VIEW, CNN_BINS = 4096, 512
 class gtls_params(ctypes.Structure):
     _fields_ = [("dt0", ctypes.c_double), ("envelope", ctypes.c_int32), ("k_min", ctypes.c_double),
                 ("k_max", ctypes.c_double), ("q_cap", ctypes.c_double), ("depth_mode", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("median_window", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("median_window", ctypes.c_int32),
+                ("batch_route_min", ctypes.c_int32)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -29,7 +29,8 @@ def test_library_exports_every_declared_symbol():
 def test_params_default():
     p = gtls.gtls_params_default()
     assert (p.dt0, p.envelope, p.k_min, p.k_max, p.q_cap) == (0.0, 1, 20.05, 620.84, 0.15)
-    assert (p.depth_mode, p.precision, p.median_window) == (gtls.GTLS_DEPTH_WLS, gtls.GTLS_FP64, 91)
+    assert (p.depth_mode, p.precision, p.median_window, p.batch_route_min) == (gtls.GTLS_DEPTH_WLS, gtls.GTLS_FP64,
+                                                                               91, 0)
 
 
 def test_null_context_is_rejected():

@@ -1,10 +1,11 @@
-"""GPU tests of the batched survey path (curves under 6000 points share one
-persistent launch, longer ones go through the single-curve kernels): every
-curve's results must equal, bit for bit, the single-curve search of that
-curve (itself bit-exact against the oracle), including ragged lengths,
-per-point errors, strided T0 grids, the moving-average depth and the FP32C
-mode; mixed batches of short and long curves match the oracle; the captured
-graph must give the same results on every replay."""
+"""GPU tests of the batched survey path (one persistent launch over many
+curves; optionally, curves above batch_route_min points through the
+single-curve kernels): every curve's results must equal, bit for bit, the
+single-curve search of that curve (itself bit-exact against the oracle),
+including ragged lengths, per-point errors, strided T0 grids, the
+moving-average depth and the FP32C mode; batches split between the two
+routes match the oracle; the captured graph must give the same results on
+every replay."""
 import os
 
 import numpy as np
@@ -102,9 +103,10 @@ def test_batch_matches_oracle(ctx, oracle):
 
 
 @pytest.mark.parametrize("dt0", [0.0, 0.1])
-def test_mixed_batch_matches_oracle(ctx, oracle, dt0):
-    """Short curves (persistent launch) and long ones (single-curve kernels)
-    in one call, interleaved, against the oracle curve by curve."""
+def test_routed_batch_matches_oracle(ctx, oracle, dt0):
+    """batch_route_min = 6000: short curves (persistent launch) and long ones
+    (single-curve kernels) in one call, interleaved, against the oracle curve
+    by curve; the same call without routing gives identical results."""
     lengths = [700, 7000, 1500, 6000, 5999, 9000]
     curves = [synth.curve_random(900 + k, n=n, inject=(k % 2 == 0)) for k, n in enumerate(lengths)]
     packed = _pack(oracle, curves, nper=40)
@@ -112,7 +114,7 @@ def test_mixed_batch_matches_oracle(ctx, oracle, dt0):
     tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 128)
     offs, t, y, dy, poffs, periods, grids = packed
     print("mixed batch vs oracle", lengths, dt0, flush=True)
-    prm = gtls.gtls_params_default(dt0=dt0)
+    prm = gtls.gtls_params_default(dt0=dt0, batch_route_min=6000)
     res = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
     for k, c in enumerate(curves):
         ref = oracle.tls_search(c["t"], c["y"], c["dy"], grids[k], durs, tm, dt0=dt0, threads=THREADS)
@@ -126,6 +128,12 @@ def test_mixed_batch_matches_oracle(ctx, oracle, dt0):
         assert res.summaries[k]["best_period"] == best and res.summaries[k]["n_evals"] == ref.n_evals, label
     again = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
     assert np.array_equal(again.chi2, res.chi2) and np.array_equal(again.sde, res.sde)
+    whole = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm,
+                                  gtls.gtls_params_default(dt0=dt0))
+    for k in ("chi2", "best_dur", "best_start", "depth", "sde"):
+        assert np.array_equal(getattr(whole, k), getattr(res, k)), k
+    for k in ("chi2_null", "sde_max", "n_evals", "n_macs", "best_period"):
+        assert np.array_equal(whole.summaries[k], res.summaries[k]), k
 
 
 def test_batch_graph_replays_on_device_buffers(ctx, oracle):

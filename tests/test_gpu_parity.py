@@ -275,6 +275,7 @@ def test_validation_errors(ctx):
         dict(tmpl=np.r_[0.0, tm[1:]]),
         dict(params=gtls.gtls_params_default(dt0=-1.0)),
         dict(params=gtls.gtls_params_default(median_window=90)),
+        dict(params=gtls.gtls_params_default(batch_route_min=-1)),
         dict(time=c["t"][:2], flux=c["y"][:2], dy=c["dy"][:2]),
     ]
     for b in bad:
