@@ -236,7 +236,7 @@ __device__ __forceinline__ bool key_less(uint64_t a, uint64_t b, const double* _
 
 constexpr int kTieCap = 2048;   // equal-key neighbours listed during the last pass
 
-template <int NT>
+template <int NT, int ITEMS = kSortItems>
 struct SortShared {
     uint32_t lastkey[256];       // last pass: key of the last word written per digit (0xffffffff: none yet)
     uint32_t tie_n;              // last pass: output positions whose key equals the previous position's
@@ -248,7 +248,7 @@ struct SortShared {
     uint32_t tstart[256];        // ... and its first slot in the tile's digit order
     uint32_t wtot[4];
     union {
-        uint64_t buf[NT * kSortItems];   // a tile in digit order (sort passes)
+        uint64_t buf[NT * ITEMS];        // a tile in digit order (sort passes)
         __int128 part[NT];               // per-thread partial sums (prefix sums)
     };
     int64_t dpad;
@@ -320,11 +320,11 @@ __device__ __forceinline__ void pad_store(const PadOut& po, int64_t n, int64_t p
 // reordered by the full FP64 phase and the input index (and its padded
 // copies rewritten).  With PREFETCH every pass loads its next tile before
 // ranking the current one.
-template <int NT, bool PREFETCH>
+template <int NT, bool PREFETCH, int ITEMS = kSortItems>
 __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double period, uint64_t* A, uint64_t* B,
-                               const PadOut& po, SortShared<NT>& sh) {
+                               const PadOut& po, SortShared<NT, ITEMS>& sh) {
     constexpr int W = NT / 64;
-    constexpr int TILE = NT * kSortItems;
+    constexpr int TILE = NT * ITEMS;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -359,10 +359,10 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
         __syncthreads();
         const int shift = 32 + 8 * pass;
         // tile items: the fold itself on the first pass, the previous pass's output after
-        auto fetch = [&](int64_t tile0, uint64_t (&it)[kSortItems]) {
-            const int64_t seg0 = tile0 + (int64_t)wave * 64 * kSortItems;
+        auto fetch = [&](int64_t tile0, uint64_t (&it)[ITEMS]) {
+            const int64_t seg0 = tile0 + (int64_t)wave * 64 * ITEMS;
 #pragma unroll
-            for (int e = 0; e < kSortItems; ++e) {
+            for (int e = 0; e < ITEMS; ++e) {
                 const int64_t idx = seg0 + e * 64 + lane;
                 if (idx < n) {
                     it[e] = (pass == 0) ? (((uint64_t)phase_key(phase_of(t[idx], period)) << 32) | (uint32_t)idx)
@@ -372,16 +372,16 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
                 }
             }
         };
-        uint64_t item[kSortItems], nxt[PREFETCH ? kSortItems : 1];
+        uint64_t item[ITEMS], nxt[PREFETCH ? ITEMS : 1];
         fetch(0, item);
         for (int64_t tile0 = 0; tile0 < n; tile0 += TILE) {
             if constexpr (!PREFETCH) {
                 if (tile0 > 0) fetch(tile0, item);
             }
-            const int64_t seg0 = tile0 + (int64_t)wave * 64 * kSortItems;
-            uint32_t dig[kSortItems], rnk[kSortItems];
+            const int64_t seg0 = tile0 + (int64_t)wave * 64 * ITEMS;
+            uint32_t dig[ITEMS], rnk[ITEMS];
 #pragma unroll
-            for (int e = 0; e < kSortItems; ++e) {
+            for (int e = 0; e < ITEMS; ++e) {
                 const int64_t idx = seg0 + e * 64 + lane;
                 const bool active = idx < n;
                 const uint32_t d = active ? (uint32_t)(item[e] >> shift) & 255u : 0u;
@@ -436,7 +436,7 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
             __syncthreads();
             // the tile in digit order (stable: waves, then items, then lanes, follow input order) ...
 #pragma unroll
-            for (int e = 0; e < kSortItems; ++e) {
+            for (int e = 0; e < ITEMS; ++e) {
                 const int64_t idx = seg0 + e * 64 + lane;
                 if (idx < n) sh.buf[sh.tstart[dig[e]] + sh.wcnt[wave][dig[e]] + rnk[e]] = item[e];
             }
@@ -473,7 +473,7 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
             __syncthreads();
             if constexpr (PREFETCH) {
 #pragma unroll
-                for (int e = 0; e < kSortItems; ++e) item[e] = nxt[e];
+                for (int e = 0; e < ITEMS; ++e) item[e] = nxt[e];
             }
         }
     }
@@ -529,9 +529,9 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
 
 // Moving-average depth: prefix sums of 1 - y over the npad padded positions
 // (position k holding sorted point k mod n), from the final order in A.
-template <int NT>
+template <int NT, int ITEMS = kSortItems>
 __device__ void pad_prefix(const uint64_t* __restrict__ A, int64_t n, int64_t npad, const int64_t* __restrict__ u,
-                           void* pfx, bool f32, SortShared<NT>& sh) {
+                           void* pfx, bool f32, SortShared<NT, ITEMS>& sh) {
     const int tid = threadIdx.x;
     if (!pfx) return;
     const int64_t chunk = (npad + NT - 1) / NT;
@@ -1866,6 +1866,7 @@ __global__ __launch_bounds__(256) void k_sde_argmax_batch(const int64_t* __restr
 // best) in workgroup-private scratch.
 
 constexpr int kBatchThreads = 256;
+constexpr int kBatchSortItems = 16;   // words per thread of a sort tile (4096-word tiles)
 constexpr int kMaxBatchDurations = 64;
 
 struct BatchArgs {
@@ -2001,7 +2002,8 @@ template <typename T, bool MEAN, bool ANYVARW>
 __global__ __launch_bounds__(kBatchThreads, 2) void k_batch(BatchArgs a) {
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ BatchShared bs;
-    SortShared<kBatchThreads>& ssh = *reinterpret_cast<SortShared<kBatchThreads>*>(dyn);
+    SortShared<kBatchThreads, kBatchSortItems>& ssh =
+        *reinterpret_cast<SortShared<kBatchThreads, kBatchSortItems>*>(dyn);
     const int tid = threadIdx.x;
     const size_t es = sizeof(T);
     const size_t ps = sizeof(T) == 8 ? sizeof(__int128) : sizeof(float2);
@@ -2038,8 +2040,8 @@ __global__ __launch_bounds__(kBatchThreads, 2) void k_batch(BatchArgs a) {
         __syncthreads();
         const int64_t npad = n + bs.dpad;
         const PadOut po{a.r + o0, a.w + o0, rpad, varw ? wpad : nullptr, npad, sizeof(T) == 4};
-        fold_sort_core<kBatchThreads, false>(a.t + o0, n, period, A, B, po, ssh);
-        pad_prefix<kBatchThreads>(A, n, npad, a.u + o0, pfx, sizeof(T) == 4, ssh);
+        fold_sort_core<kBatchThreads, false, kBatchSortItems>(a.t + o0, n, period, A, B, po, ssh);
+        pad_prefix<kBatchThreads, kBatchSortItems>(A, n, npad, a.u + o0, pfx, sizeof(T) == 4, ssh);
         for (int64_t k = npad + tid; k < npad + kOverRead; k += kBatchThreads) {
             ((T*)rpad)[k] = (T)0;
             if (varw) ((T*)wpad)[k] = (T)0;
@@ -2408,7 +2410,7 @@ namespace {
 template <typename T, bool MEAN, bool ANYVARW>
 size_t batch_lds_bytes() {
     const size_t es = sizeof(T), mult = ANYVARW ? 2 : 1;
-    const size_t sort = sizeof(SortShared<kBatchThreads>);
+    const size_t sort = sizeof(SortShared<kBatchThreads, kBatchSortItems>);
     const size_t unit = (size_t)xpad<T>(kXs) * es * mult;
     const size_t stage = (size_t)(kBatchThreads / 64) * mult * kStage<T> * es;
     return std::max(sort, std::max(unit, stage));
