@@ -2251,9 +2251,13 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
                  (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
                  sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles +
                  (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kTaskMax + 1024;
-    const size_t budget = (size_t)24 << 30;
+    // Periods per launch: as many as 72 GiB of scratch hold (a quarter of
+    // the HBM), at most 32768.  Fewer, larger launches leave fewer drained
+    // tails: on the 3000-day grid, 19 launches instead of 55 (with 24 GiB and
+    // 8192) cut the sort by 9 % and the strided slide by 4 %.
+    const size_t budget = (size_t)72 << 30;
     int64_t bp = (int64_t)(budget / per);
-    bp = std::max<int64_t>(1, std::min<int64_t>(bp, 8192));
+    bp = std::max<int64_t>(1, std::min<int64_t>(bp, 32768));
     bp = std::min<int64_t>(bp, n_periods);
     // one-dimensional grids of bp * nd * ntiles work units
     const int64_t units = std::max<int64_t>(1, (int64_t)nd * p.ntiles);
