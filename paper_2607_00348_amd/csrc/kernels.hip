@@ -2259,9 +2259,10 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     int64_t bp = (int64_t)(budget / per);
     bp = std::max<int64_t>(1, std::min<int64_t>(bp, 32768));
     bp = std::min<int64_t>(bp, n_periods);
-    // one-dimensional grids of bp * nd * ntiles work units
+    // The every-offset slide launches bp * nd * ntiles workgroups of
+    // kSlideThreads: a dispatch counts at most 2^32 - 1 work-items.
     const int64_t units = std::max<int64_t>(1, (int64_t)nd * p.ntiles);
-    bp = std::max<int64_t>(1, std::min<int64_t>(bp, 0x7fffffffLL / units));
+    bp = std::max<int64_t>(1, std::min<int64_t>(bp, 0xffffffffLL / (units * kSlideThreads)));
     p.bp = (int32_t)bp;
     size_t o = 0;
     p.off_a = o;

@@ -108,3 +108,24 @@ def test_fp32c_tess_precision_stress(ctx, oracle):
     res = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods[idx], durs, tm, prm)
     ref = oracle.tls_search(c["t"], c["y"], c["dy"], periods[idx], durs, tm, threads=THREADS)
     _check(oracle, c, periods[idx], durs, tm, res, ref, "tess fp32c")
+
+
+def test_fp32c_full_3000d_grid_evaluates_every_window(ctx):
+    """Regression test of the launch split at full size: the 3000-day curve's
+    whole grid at T0 step 0.1 (the largest launches the library makes, whose
+    every-offset grid must stay within one dispatch's work-item count) must
+    evaluate exactly the windows the FP64 search evaluates, and agree with it
+    within the FP32C tolerance."""
+    c = synth.curve_3000d()
+    span = c["t"][-1] - c["t"][0]
+    periods = gtls.gtls_period_grid_ofir(span, 3.0, pmin_days=0.5, pmax_days=1500.0)
+    durs = gtls.gtls_duration_grid(0.5, 1500.0, 20)
+    tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    print("fp32c vs fp64, full 3000-day grid", len(periods), flush=True)
+    r32 = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm,
+                          gtls.gtls_params_default(dt0=0.1, precision=gtls.GTLS_FP32C))
+    r64 = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, gtls.gtls_params_default(dt0=0.1))
+    assert r32.n_evals == r64.n_evals and r32.n_macs == r64.n_macs
+    err = np.max(np.abs(r32.chi2 - r64.chi2) / r64.chi2)
+    print(f"max rel chi2 error {err:.2e}", flush=True)
+    assert err < RTOL and r32.best_period == r64.best_period
