@@ -2234,7 +2234,7 @@ struct Plan {
     size_t off_a, off_b, off_r, off_w, off_pf, off_items, off_toff, off_tmap, off_sb, off_queue, per_batch;
 };
 
-Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm, bool varw) {
+Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm, bool varw, size_t budget) {
     Plan p{};
     p.n = n;
     p.varw = varw;
@@ -2251,11 +2251,10 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
                  (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
                  sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles +
                  (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kTaskMax + 1024;
-    // Periods per launch: as many as 72 GiB of scratch hold (a quarter of
-    // the HBM), at most 32768.  Fewer, larger launches leave fewer drained
-    // tails: on the 3000-day grid, 19 launches instead of 55 (with 24 GiB and
-    // 8192) cut the sort by 9 % and the strided slide by 4 %.
-    const size_t budget = (size_t)72 << 30;
+    // Periods per launch: as many as the scratch budget holds, at most
+    // 32768.  Fewer, larger launches leave fewer drained tails: on the
+    // 3000-day grid, 19 launches instead of 55 (72 GiB against 24 GiB of
+    // scratch) cut the sort by 9 % and the strided slide by 4 %.
     int64_t bp = (int64_t)(budget / per);
     bp = std::max<int64_t>(1, std::min<int64_t>(bp, 32768));
     bp = std::min<int64_t>(bp, n_periods);
@@ -2349,7 +2348,16 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     if (e != hipSuccess) return e;
     const bool varw = hmisc[kWminBits] != hmisc[kWmaxBits];
 
-    const Plan pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw);
+    // Scratch budget: 72 GiB (a quarter of the HBM), at most half of what
+    // the device has free beside the context's current period scratch; on
+    // an allocation failure the budget halves and the plan is redone.
+    size_t budget = (size_t)72 << 30;
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+            budget = std::min(budget, (free_b + ctx->batch.bytes) / 2);
+    }
+    Plan pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw, budget);
     // Template rows for every D in [1, dcap] and the per-D sums.
     const size_t tab_elems = (size_t)trow_off(pl.dcap + 1);
     const size_t off_bsum = align256(pl.esize * tab_elems), off_s1 = align256(off_bsum + 8 * (size_t)(pl.dcap + 1));
@@ -2366,6 +2374,12 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
         else k_tmpl_sums<double><<<(unsigned)((pl.dcap + 63) / 64), 64, 0, s>>>((const double*)table, pl.dcap, misc, bsum, s1sum);
     }
     e = ensure(ctx, ctx->batch, pl.per_batch);
+    while (e == hipErrorOutOfMemory && pl.bp > 1) {
+        (void)hipGetLastError();
+        budget /= 2;
+        pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw, budget);
+        e = ensure(ctx, ctx->batch, pl.per_batch);
+    }
     if (e != hipSuccess) return e;
     char* bb = (char*)ctx->batch.ptr;
     uint64_t* keys_a = (uint64_t*)(bb + pl.off_a);
@@ -2615,16 +2629,33 @@ static hipError_t run_search_batch_queued(gtls_ctx* ctx, const BatchArgsHost& h,
 
     // The rest of the pipeline runs as one captured graph, replayed while
     // the arguments stay the same.
+    // The key holds every value a captured launch reads from its arguments:
+    // all parameters (their bytes), every device pointer of the kernels and
+    // every size, so a call that changes any of them captures a new graph.
     std::vector<uint64_t> key = shape;
-    for (const void* p : {(const void*)h.t, (const void*)h.periods, (const void*)h.durations, (const void*)h.tmpl,
-                          (const void*)h.chi2, (const void*)h.sde, (const void*)h.summaries, (const void*)cb,
-                          (const void*)sb, (const void*)ctx->table.ptr})
+    {
+        const gtls_params& pp = h.prm;
+        for (const double v : {pp.dt0, pp.k_min, pp.k_max, pp.q_cap}) {
+            uint64_t b = 0;
+            std::memcpy(&b, &v, sizeof(b));
+            key.push_back(b);
+        }
+        for (const int32_t v : {pp.envelope, pp.depth_mode, pp.precision, pp.median_window, pp.batch_route_min})
+            key.push_back((uint64_t)(uint32_t)v);
+    }
+    for (const void* p : {(const void*)h.t, (const void*)h.y, (const void*)h.dy, (const void*)h.periods,
+                          (const void*)h.durations, (const void*)h.tmpl, (const void*)h.chi2,
+                          (const void*)h.best_dur, (const void*)h.best_start, (const void*)h.depth,
+                          (const void*)h.t0, (const void*)h.sr, (const void*)h.sde_raw, (const void*)h.sde,
+                          (const void*)h.summaries, (const void*)cb, (const void*)sb, (const void*)ctx->table.ptr,
+                          (const void*)ba.w, (const void*)ba.r, (const void*)ba.u, (const void*)ba.cmisc,
+                          (const void*)ba.s1sum, (const void*)ba.order, (const void*)ba.qoff, (const void*)ba.queue,
+                          (const void*)ba.scr_a, (const void*)ba.scr_b, (const void*)ba.scr_r, (const void*)ba.scr_w,
+                          (const void*)ba.scr_pf, (const void*)ba.cevals})
         key.push_back((uint64_t)(uintptr_t)p);
-    key.push_back((uint64_t)nc);
-    key.push_back((uint64_t)nq);
-    key.push_back((uint64_t)total_items);
-    key.push_back((uint64_t)grid);
-    key.push_back((uint64_t)h.prm.median_window);
+    for (const int64_t v : {(int64_t)nc, (int64_t)nq, (int64_t)h.nd, (int64_t)h.nt, total_items, total_periods,
+                            (int64_t)grid, n_max, pstride, dcap, ba.scr_n, ba.scr_pstride, ba.item_limit})
+        key.push_back((uint64_t)v);
     for (int c = 0; c <= nc; ++c) {
         key.push_back((uint64_t)h.offsets[c]);
         key.push_back((uint64_t)h.poffsets[c]);
@@ -2665,7 +2696,7 @@ hipError_t run_fold_sort(gtls_ctx* ctx, const double* t, int64_t n, const double
     hipStream_t s = ctx->stream;
     gtls_params prm;
     gtls_params_default(&prm);
-    const Plan pl = make_plan(n, n_periods, 1, prm, false);
+    const Plan pl = make_plan(n, n_periods, 1, prm, false, (size_t)8 << 30);
     hipError_t e = ensure(ctx, ctx->batch, pl.per_batch);
     if (e != hipSuccess) return e;
     char* bb = (char*)ctx->batch.ptr;

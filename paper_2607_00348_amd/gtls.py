@@ -77,12 +77,50 @@ class GtlsError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes() -> list:
+    """Paths of the HIP runtime libraries (libamdhip64) mapped into this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 6 and os.path.basename(parts[5]).startswith("libamdhip64.so"):
+                    found.add(os.path.realpath(parts[5]))
+    except OSError:
+        pass
+    return sorted(found)
+
+
+def _load_host_runtime_first() -> None:
+    """Make the library share the HIP runtime of PyTorch when PyTorch is installed.
+
+    libgtls.so needs the runtime by its soname (libamdhip64.so.7, found through
+    its RUNPATH in the ROCm install).  PyTorch's HIP libraries need the
+    unversioned name libamdhip64.so, which they resolve to the copy shipped in
+    torch/lib; that copy carries the same soname.  Loaded in the order torch,
+    then libgtls, the dynamic loader matches libgtls's need against the soname
+    already present and both use torch's copy.  In the other order the process
+    ends up with two HIP runtimes (and two HSA runtimes) whose device pointers
+    and streams are not interchangeable, which breaks every call that receives
+    a torch tensor's address or torch's stream.  So torch is imported first.
+    """
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        _load_host_runtime_first()
         L = ctypes.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError(f"two HIP runtimes are mapped into this process ({', '.join(rts)}); "
+                               "load libgtls.so after PyTorch, never before it")
         vp = ctypes.c_void_p
         L.gtls_create.restype = ctypes.c_int
         L.gtls_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]

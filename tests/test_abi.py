@@ -80,3 +80,35 @@ def test_helpers_reject_bad_arguments():
         gtls.gtls_duration_grid(2.0, 1.0, 5)
     with pytest.raises(gtls.GtlsError):
         gtls.gtls_template_quadratic(0.4, 0.25, 0.0, 0.0, 64)
+
+
+def _run_py(code: str) -> str:
+    import subprocess
+    import sys
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    return out.stdout
+
+
+def test_one_hip_runtime_when_library_loads_before_torch():
+    """Loading the binding first and PyTorch afterwards must leave a single
+    HIP runtime mapped (no GPU is touched: only the loader runs)."""
+    out = _run_py("from paper_2607_00348_amd import gtls\n"
+                  "gtls.lib()\n"
+                  "import torch\n"
+                  "print('\\n'.join(gtls._hip_runtimes()))\n")
+    maps = [l for l in out.splitlines() if l.strip()]
+    assert len(maps) == 1, maps
+
+
+def test_two_runtimes_are_detected():
+    """The failure the binding avoids: libgtls.so opened directly, before
+    PyTorch, maps the ROCm install's runtime and then torch's own copy."""
+    out = _run_py("import ctypes\n"
+                  "from paper_2607_00348_amd import gtls\n"
+                  "ctypes.CDLL(gtls.LIB_PATH)\n"
+                  "import torch\n"
+                  "print('\\n'.join(gtls._hip_runtimes()))\n")
+    maps = [l for l in out.splitlines() if l.strip()]
+    assert len(maps) == 2, maps

@@ -180,6 +180,62 @@ def test_batch_graph_replays_on_device_buffers(ctx, oracle):
     dctx.close()
 
 
+def test_batch_graph_key_covers_params_and_outputs(ctx, oracle):
+    """A second device-pointer call on the same context that changes only
+    the duration envelope (q_cap, k_max) and writes into freshly allocated
+    outputs (the first call's outputs kept alive) must capture a new graph:
+    its results equal a fresh context's search with the new parameters, and
+    the first call's outputs stay untouched."""
+    import torch
+    curves = _curves(43, 5, 800, 5000)
+    packed = _pack(oracle, curves, nper=60)
+    offs, t, y, dy, poffs, periods, grids = packed
+    durs = oracle.duration_grid(0.5, 100.0, 10)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 128)
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    t_d, y_d, dy_d, p_d, d_d, tm_d = f(t), f(y), f(dy), f(periods), f(durs), f(tm)
+    npd = len(periods)
+
+    def outputs():
+        o = {k: torch.empty(npd, dtype=torch.float64, device=dev) for k in ("chi2", "depth", "t0", "sr", "raw", "sde")}
+        o["bd"] = torch.empty(npd, dtype=torch.int32, device=dev)
+        o["bs"] = torch.empty(npd, dtype=torch.int32, device=dev)
+        o["summ"] = torch.zeros(len(curves) * 5, dtype=torch.int64, device=dev)
+        return o
+
+    def run(dctx, prm, o):
+        gtls.tls_search_batch_dev(dctx, offs, t_d.data_ptr(), y_d.data_ptr(), dy_d.data_ptr(), poffs,
+                                  p_d.data_ptr(), d_d.data_ptr(), len(durs), tm_d.data_ptr(), len(tm), prm,
+                                  o["chi2"].data_ptr(), o["bd"].data_ptr(), o["bs"].data_ptr(),
+                                  o["depth"].data_ptr(), o["t0"].data_ptr(), o["sr"].data_ptr(),
+                                  o["raw"].data_ptr(), o["sde"].data_ptr(), o["summ"].data_ptr())
+        torch.cuda.synchronize()
+        return o["chi2"].cpu().numpy().copy(), o["bd"].cpu().numpy().copy(), o["bs"].cpu().numpy().copy()
+
+    stream = torch.cuda.current_stream()
+    dctx = gtls.Context(0, stream.cuda_stream)
+    p1 = gtls.gtls_params_default(dt0=0.1)
+    p2 = gtls.gtls_params_default(dt0=0.1, q_cap=0.05, k_max=300.0)
+    o1 = outputs()
+    print("graph key: first call", flush=True)
+    first = run(dctx, p1, o1)
+    o2 = outputs()
+    print("graph key: second call, new envelope and outputs", flush=True)
+    second = run(dctx, p2, o2)
+    dctx.close()
+    ref1 = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, p1)
+    fresh = gtls.Context(0)
+    ref2 = gtls.tls_search_batch(fresh, offs, t, y, dy, poffs, periods, durs, tm, p2)
+    fresh.close()
+    assert not np.array_equal(ref1.best_dur, ref2.best_dur)       # the envelope change matters
+    assert np.array_equal(second[0], ref2.chi2)
+    assert np.array_equal(second[1], ref2.best_dur)
+    assert np.array_equal(second[2], ref2.best_start)
+    assert np.array_equal(o1["chi2"].cpu().numpy(), first[0])    # first outputs untouched
+    assert np.array_equal(first[0], ref1.chi2) and np.array_equal(first[1], ref1.best_dur)
+
+
 def test_batch_validation(ctx):
     c = synth.curve_random(5, n=100)
     tm = np.linspace(0.5, 1.0, 16)
