@@ -20,6 +20,16 @@ What it computes:
 
 Parameters travel as one flat vector in the order W0, b0, ..., W4, b4, Wf,
 bf with W_l of shape (32, C_in, 7) and Wf of shape (512, 32).
+
+Storage precision.  ``forward`` and ``loss_and_grad`` take an optional
+``rnd`` function.  It models a precision scheme that multiplies reduced-
+precision operands with a wider accumulation (the learned proposal is
+specified with BF16 operands and FP32 accumulation): it is applied to every
+tensor that such a scheme stores as a matrix operand -- the network input, the
+GELU outputs that feed the next convolution, and the back-propagated
+pre-activation gradients dz of every layer before they enter the weight,
+bias and data gradients.  Weights are rounded by the caller.  The default
+(None) keeps everything in FP64.
 """
 from __future__ import annotations
 
@@ -99,25 +109,33 @@ def _conv(h, w, b):
     return z + b[None, :, None]
 
 
-def forward(p, x):
+def _keep(a):
+    return a
+
+
+def forward(p, x, rnd=None):
     """x: (B, 4096) views -> (logits (B, 512), cache)."""
+    rnd = rnd or _keep
     layers = unflatten(np.asarray(p, dtype=np.float64))
-    h = np.asarray(x, dtype=np.float64)[:, None, :]
+    h = rnd(np.asarray(x, dtype=np.float64))[:, None, :]
     cache = []
-    for w, b in layers[:NL]:
+    for li, (w, b) in enumerate(layers[:NL]):
         z = _conv(h, w, b)
         cache.append((h, z))
         h = _gelu(z)
+        if li < NL - 1:
+            h = rnd(h)
     g = h.mean(axis=2)
     wf, bf = layers[NL]
     logits = g @ wf.T + bf
     return logits, (cache, h, g)
 
 
-def loss_and_grad(p, x, labels):
+def loss_and_grad(p, x, labels, rnd=None):
     """Mean softmax cross-entropy and its gradient (flat, like p)."""
+    rnd = rnd or _keep
     layers = unflatten(np.asarray(p, dtype=np.float64))
-    logits, (cache, h_last, g) = forward(p, x)
+    logits, (cache, h_last, g) = forward(p, x, rnd)
     n = logits.shape[0]
     m = logits.max(axis=1, keepdims=True)
     e = np.exp(logits - m)
@@ -135,7 +153,7 @@ def loss_and_grad(p, x, labels):
     for li in range(NL - 1, -1, -1):
         h, z = cache[li]
         w, b = layers[li]
-        dz = dh * _gelu_grad(z)
+        dz = rnd(dh * _gelu_grad(z))
         hp = np.zeros((n, h.shape[1], L + KW - 1))
         hp[:, :, KW // 2:KW // 2 + L] = h
         dw = np.zeros_like(w)

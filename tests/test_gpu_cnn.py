@@ -1,12 +1,20 @@
 """GPU tests of the learned period proposal's hand-written kernels against the
 FP64 CPU reference (oracle/cnn.py).
 
-The GPU multiplies BF16 operands with FP32 accumulation and keeps layer
-activations in BF16, so the reference is evaluated on the same BF16-rounded
-conv weights and inputs and the bar follows from BF16 rounding (8 bits of
-mantissa, relative 2^-9 per rounding, compounded over five layers): logits
-within 3 % of their range, gradients with cosine similarity >= 0.995 and
-relative L2 error <= 5 % per tensor.  The view is compared exactly."""
+The GPU multiplies BF16 operands with FP32 accumulation: the input view, the
+conv weights, the GELU outputs that feed the next convolution and the
+back-propagated pre-activation gradients are stored as BF16.  The reference
+is evaluated on the same BF16-rounded weights and inputs with the same
+storage roundings (the oracle's ``rnd`` hook, each value rounded from FP32 to
+BF16 with round-to-nearest-even), so what is left is FP32 against FP64
+accumulation and FP32 transcendental functions, plus the rare BF16 rounding
+that an FP32 and an FP64 value near a rounding boundary take differently.
+Element-wise bars: logits |gpu - ref| <= 1e-3 |ref| + 1e-5 max|ref|; each
+gradient tensor |gpu - ref| <= 1e-2 |ref| + 1e-3 max|ref| (the absolute term
+covers elements near zero whose sums of B x 4096 products cancel: FP32
+accumulation leaves about sqrt(n) 2^-24 of the sum of magnitudes, a flipped
+BF16 rounding moves one product by 2^-8).  The Adam update is compared with
+the reference update from the same gradients.  The view is compared exactly."""
 import numpy as np
 import pytest
 
@@ -53,6 +61,19 @@ def test_view_matches_oracle(ctx):
         assert np.array_equal(v[k], ref), k
 
 
+def _bf16_store(a):
+    """BF16 storage of a value computed in FP32 (round to nearest even)."""
+    return _bf16(np.asarray(a, dtype=np.float64).astype(np.float32)).astype(np.float64)
+
+
+def _tensors(flat):
+    o = 0
+    for l, (ws, bs) in enumerate(cnn.SHAPES):
+        for n_el, name in ((int(np.prod(ws)), "W"), (int(np.prod(bs)), "b")):
+            yield l, name, slice(o, o + n_el)
+            o += n_el
+
+
 def test_forward_and_gradients_match_oracle(ctx):
     p = synth.cnn_init(11).astype(np.float32)
     p[-512:] = synth.rng(12).normal(0, 0.05, 512)
@@ -63,22 +84,47 @@ def test_forward_and_gradients_match_oracle(ctx):
     lg = gtls.gtls_cnn_forward(net, views)
     loss, gr = gtls.gtls_cnn_gradients(net, views, labels)
     q = _effective_params(p)
-    ref_lg, _ = cnn.forward(q, views.astype(np.float64))
-    ref_loss, ref_gr = cnn.loss_and_grad(q, views.astype(np.float64), labels)
-    span = ref_lg.max() - ref_lg.min()
-    err = np.max(np.abs(lg - ref_lg)) / span
-    print(f"logits rel err {err:.2e} (range {span:.3f}); loss {loss:.5f} vs {ref_loss:.5f}", flush=True)
-    assert err <= 3e-2
-    assert abs(loss - ref_loss) <= 3e-2 * abs(ref_loss)
-    o = 0
-    for l, (ws, bs) in enumerate(cnn.SHAPES):
-        for n_el, name in ((int(np.prod(ws)), "W"), (int(np.prod(bs)), "b")):
-            a, b = gr[o:o + n_el].astype(np.float64), ref_gr[o:o + n_el]
-            o += n_el
-            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
-            rel = float(np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-300))
-            print(f"layer {l} {name}: cosine {cos:.5f}, rel L2 {rel:.2e}", flush=True)
-            assert cos >= 0.995 and rel <= 5e-2, (l, name, cos, rel)
+    ref_lg, _ = cnn.forward(q, views.astype(np.float64), rnd=_bf16_store)
+    ref_loss, ref_gr = cnn.loss_and_grad(q, views.astype(np.float64), labels, rnd=_bf16_store)
+    lim = 1e-3 * np.abs(ref_lg) + 1e-5 * np.abs(ref_lg).max()
+    worst = float(np.max(np.abs(lg - ref_lg) / lim))
+    print(f"logits: worst |err| / bound {worst:.3f}; loss {loss:.7f} vs {ref_loss:.7f}", flush=True)
+    assert worst <= 1.0
+    assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss)
+    for l, name, sl in _tensors(gr):
+        a, b = gr[sl].astype(np.float64), ref_gr[sl]
+        lim = 1e-2 * np.abs(b) + 1e-3 * np.abs(b).max()
+        ratio = np.abs(a - b) / lim
+        print(f"layer {l} {name}: worst |err| / bound {ratio.max():.3f}, "
+              f"max rel err {np.max(np.abs(a - b)) / np.abs(b).max():.2e}", flush=True)
+        assert ratio.max() <= 1.0, (l, name, int(np.argmax(ratio)))
+    net.close()
+
+
+def test_adam_matches_oracle(ctx):
+    """Three Adam steps on the GPU against the reference update (FP64) fed
+    with the GPU's own gradients at each step's parameters."""
+    p = synth.cnn_init(31).astype(np.float32)
+    g = synth.rng(32)
+    views = g.normal(0, 1, (4, cnn.L)).astype(np.float32)
+    labels = g.integers(0, cnn.NB, 4).astype(np.int32)
+    net = gtls.Cnn(ctx, p)
+    q = p.astype(np.float64)
+    m = np.zeros(cnn.N_PARAMS)
+    v = np.zeros(cnn.N_PARAMS)
+    lr = 2e-3
+    for step in (1, 2, 3):
+        cur = gtls.gtls_cnn_get_params(net)
+        _, gr = gtls.gtls_cnn_gradients(net, views, labels)
+        q, m, v = cnn.adam(q, gr.astype(np.float64), m, v, step, lr=lr)
+        gtls.gtls_cnn_train_step(net, views, labels, lr=lr)
+        got = gtls.gtls_cnn_get_params(net).astype(np.float64)
+        moved = got - cur
+        want = q - cur
+        err = np.max(np.abs(moved - want)) / lr
+        print(f"adam step {step}: max |update error| / lr {err:.2e}", flush=True)
+        assert np.allclose(got, q, rtol=1e-6, atol=1e-3 * lr)
+        q = got                               # continue from the GPU's FP32 parameters
     net.close()
 
 

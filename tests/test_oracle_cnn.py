@@ -69,6 +69,61 @@ def test_matches_pytorch_autograd():
     assert np.allclose(ol, logits.detach().numpy(), rtol=1e-12, atol=1e-13)
 
 
+def _coarse(a):
+    """A deliberately coarse rounding (to multiples of 2^-6) so that a
+    rounding applied at the wrong place changes the result visibly."""
+    return np.round(np.asarray(a, dtype=np.float64) * 64.0) / 64.0
+
+
+class _RoundValue(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        return torch.from_numpy(_coarse(x.detach().numpy()))
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundGrad(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return torch.from_numpy(_coarse(g.detach().numpy()))
+
+
+def test_storage_rounding_matches_pytorch_autograd():
+    """The reduced-precision storage scheme (rounded input, rounded GELU
+    outputs between layers, rounded pre-activation gradients) against
+    PyTorch-CPU autograd with the same roundings inserted as autograd
+    functions: rounding of a value in the forward pass (identity gradient)
+    and rounding of the gradient reaching each convolution's output."""
+    p = synth.cnn_init(17)
+    p[cnn.N_PARAMS - 512:] = synth.rng(18).normal(0, 0.1, 512)
+    x, lab = _batch(19, n=2)
+    x = x * 3.0
+    loss, gr = cnn.loss_and_grad(p, x, lab, rnd=_coarse)
+    ts = _torch_net(p)
+    h = _RoundValue.apply(torch.tensor(x, dtype=torch.float64))[:, None, :]
+    for li, (w, b) in enumerate(ts[:cnn.NL]):
+        z = _RoundGrad.apply(torch.nn.functional.conv1d(h, w, b, padding=3))
+        h = torch.nn.functional.gelu(z, approximate="none")
+        if li < cnn.NL - 1:
+            h = _RoundValue.apply(h)
+    logits = torch.nn.functional.linear(h.mean(dim=2), ts[cnn.NL][0], ts[cnn.NL][1])
+    tl = torch.nn.functional.cross_entropy(logits, torch.tensor(lab))
+    tl.backward()
+    tg = np.concatenate([np.concatenate([w.grad.numpy().ravel(), b.grad.numpy().ravel()]) for w, b in ts])
+    assert abs(loss - tl.item()) < 1e-12 * abs(loss)
+    assert np.allclose(gr, tg, rtol=1e-9, atol=1e-14)
+    # the rounding matters at this scale: the FP64 gradient differs
+    _, g64 = cnn.loss_and_grad(p, x, lab)
+    assert not np.allclose(gr, g64, rtol=1e-3, atol=1e-6)
+
+
 def test_adam_matches_torch():
     g = synth.rng(9)
     p = g.normal(0, 1, 50)

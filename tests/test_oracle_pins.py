@@ -536,3 +536,58 @@ def test_transit_stats_scale_invariance(oracle):
     assert np.array_equal(p0["depth"], p1["depth"]) and np.array_equal(p0["epoch"], p1["epoch"])
     assert np.array_equal(p0["sigma"] * 4.0, p1["sigma"])
     assert st0["snr"] == st1["snr"] * 4.0 and st0["depth_odd"] == st1["depth_odd"]
+
+
+@pytest.mark.parametrize("start,d", [(0, 50), (333, 41), (1265, 30), (1275, 20), (1279, 7)])
+def test_transit_stats_mid_times_exact(oracle, start, d):
+    """Phase of the window's middle point and per-transit mid-times on a grid
+    where every phase is a multiple of 1/128 (P = 2 d, cadence 1/64 d, ten
+    epochs): the sorted order is known in closed form (phase bin, then
+    epoch), so phase_mid and t_mid = (epoch + phase_mid) P follow exactly,
+    with exact rational arithmetic, for windows whose middle point lies
+    before the end of the sorted curve and for wrapped ones (middle point
+    past the end: phase + 1, epochs counted one lower)."""
+    period, per_epoch, epochs = 2.0, 128, 10
+    n = per_epoch * epochs
+    k = np.arange(n)
+    t = k / 64.0
+    y = np.ones(n)
+    dy = np.full(n, 1e-3)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.05, 0.0, 64)
+    st, per = oracle.transit_stats(t, y, dy, period, d, start, tm)
+
+    def point_at(p):                     # input index at sorted position p (closed form)
+        q = p % n
+        return (q % epochs) * per_epoch + q // epochs
+
+    pm = start + d // 2
+    want_phase = Fraction(point_at(pm) % per_epoch, per_epoch) + (1 if pm >= n else 0)
+    assert Fraction(st["phase_mid"]) == want_phase
+    eps = sorted({point_at(p) // per_epoch - (1 if p >= n else 0) for p in range(start, start + d)})
+    assert list(per["epoch"]) == eps
+    for e, tmid in zip(per["epoch"], per["t_mid"]):
+        assert Fraction(tmid) == (int(e) + want_phase) * Fraction(period)
+    assert oracle.fold_sort(t, period)[pm % n] == point_at(pm)
+
+
+def test_transit_stats_mid_times_at_injected_transits(oracle):
+    """Noiseless curve with a symmetric transit every period: at the search's
+    best window the reported mid-time of every transit lies within one
+    cadence of the injected mid-time T0 + e P (the window is centred on the
+    transit, and its middle point is the data point nearest the centre)."""
+    cad = 0.02
+    t = np.arange(0.0, 60.0, cad)
+    tr = dict(period=5.3, t0=1.37, t14=0.24, depth=2e-3, u1=0.4, u2=0.25, b=0.0)
+    y = 1.0 - synth.transit_deficit(t, **tr)
+    dy = np.full(len(t), 1e-4)
+    tm = oracle.template_quadratic(0.4, 0.25, math.sqrt(2e-3), 0.0, 256)
+    periods = np.array([tr["period"]])
+    durs = np.array([tr["t14"]])
+    ref = oracle.tls_search(t, y, dy, periods, durs, tm, envelope=0, q_cap=0.15, threads=1)
+    d = oracle.points_in_duration(len(t), tr["period"], tr["t14"])
+    st, per = oracle.transit_stats(t, y, dy, tr["period"], d, int(ref.best_start[0]), tm)
+    assert st["n_transits"] >= 11
+    for e, tmid in zip(per["epoch"], per["t_mid"]):
+        assert abs(tmid - (tr["t0"] + e * tr["period"])) <= cad, (e, tmid)
+    # the search's T0 is the first of these mid-times at or after min(t)
+    assert abs(ref.t0[0] - tr["t0"]) <= cad
