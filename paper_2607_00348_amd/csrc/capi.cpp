@@ -48,10 +48,6 @@ gtls_status check_sizes(gtls_ctx* ctx, int64_t n, int32_t np, int32_t nd, int32_
     if (np < 1) return fail(ctx, GTLS_EINVAL, "n_periods must be >= 1");
     if (nd < 1) return fail(ctx, GTLS_EINVAL, "n_durations must be >= 1");
     if (nt < 2) return fail(ctx, GTLS_EINVAL, "n_tmpl must be >= 2");
-    // one period's every-offset slide is nd x ceil(n / 4096) workgroups of
-    // 256 work-items, and one dispatch counts at most 2^32 - 1 work-items
-    if ((int64_t)nd * ((n + 4095) / 4096) * 256 > 0xffffffffLL)
-        return fail(ctx, GTLS_EINVAL, "n_durations x ceil(n / 4096) must not exceed 2^24 - 1");
     return GTLS_OK;
 }
 

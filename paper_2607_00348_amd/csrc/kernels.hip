@@ -752,9 +752,14 @@ struct SlideArgs {
     int32_t* toff;           // [bp nd + 1] first task of item (jrev bp + pl); last = total
     int32_t* tmap;           // [bp nd kTaskMax] item of task
     ItemBest* sb;            // [bp nd kTaskMax] best of task
-    uint32_t* queue;         // [2 kXcds + 1] pop counters, queue starts, total
+    uint32_t* queue;         // [2 kXcds + 2] pop counters, queue starts, total, unit-item count
     int32_t rmax;            // most windows per lane (the FP32C rule keeps it at 4)
     int32_t rcost;           // 1: windows per lane by the wave-chunk count (FP64), 0: the FP32C rule
+    // Every-offset items (stride 1), listed by the planner: item pl nd + j,
+    // longest durations first, then period.
+    int32_t* ulist;          // [bp nd]
+    int32_t* cnt;            // [bp nd] planner scratch: tasks per item in queue order
+    int32_t* ucnt;           // [bp nd] planner scratch: 1 per every-offset item in list order
 };
 
 struct Best {
@@ -807,24 +812,6 @@ struct ItemInfo {
     int64_t d, stride;
 };
 
-// Work units in launch order: longest durations first, then window tile,
-// then period, so the costliest units start earliest.
-__device__ __forceinline__ ItemInfo item_info(const SlideArgs& a, int tiles) {
-    ItemInfo it;
-    const int per_j = tiles * a.bp;
-    const int jrev = blockIdx.x / per_j;
-    const int rem = blockIdx.x - jrev * per_j;
-    it.tile = rem / a.bp;
-    it.pl = rem - it.tile * a.bp;
-    it.j = a.nd - 1 - jrev;
-    it.period = a.periods[it.pl];
-    const double dur = a.durations[it.j];
-    it.valid = duration_valid(it.period, dur, a.prm);
-    it.d = it.valid ? points_in(a.n, it.period, dur) : 0;
-    it.stride = it.valid ? t0_stride(it.d, a.prm.dt0) : 1;
-    return it;
-}
-
 __device__ __forceinline__ ItemBest* item_slot(const SlideArgs& a, const ItemInfo& it) {
     return a.items + ((size_t)it.pl * a.nd + it.j) * a.ntiles + it.tile;
 }
@@ -840,18 +827,6 @@ __device__ __forceinline__ void store_best(const Best& b, const SlideArgs& a, co
         out->d = (int32_t)it.d;
         out->evals = (int32_t)evals;
         if (it.tile == 0) out->ntiles = ntiles;
-    }
-}
-
-__device__ __forceinline__ void store_invalid(const SlideArgs& a, const ItemInfo& it) {
-    if (threadIdx.x == 0 && it.tile == 0) {
-        ItemBest* out = item_slot(a, it);
-        out->dchi2 = -INFINITY;
-        out->depth = 0.0;
-        out->start = -1;
-        out->d = 0;
-        out->evals = 0;
-        out->ntiles = 1;
     }
 }
 
@@ -1406,25 +1381,35 @@ __device__ __forceinline__ SlideItem make_item(const SlideArgs& a, const ItemInf
     return si;
 }
 
+constexpr int kPlanThreads = 1024;
+constexpr int kXcds = 8;                 // MI355X: workgroups go round-robin over 8 XCDs (L2 domains)
+
+// Every-offset items: work unit u = (list entry u / ntiles, window tile
+// u mod ntiles), taken in list order by a grid-stride loop, so a launch is
+// sized by the work and not by the period x duration grid.
 template <typename T, bool VARW, bool MEAN>
 __global__ __launch_bounds__(kSlideThreads) void k_slide_unit(SlideArgs a) {
     __shared__ T x_sh[xpad<T>(kXs)];
     __shared__ T xw_sh[VARW ? xpad<T>(kXs) : 1];
     __shared__ Best red[kSlideThreads / 64];
-    const ItemInfo it = item_info(a, a.ntiles);
-    if (!it.valid) {
-        store_invalid(a, it);
-        return;
+    const int64_t units = (int64_t)a.queue[2 * kXcds + 1] * a.ntiles;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int32_t item = a.ulist[u / a.ntiles];
+        ItemInfo it;
+        it.pl = item / a.nd;
+        it.j = item - it.pl * a.nd;
+        it.tile = (int)(u % a.ntiles);
+        it.period = a.periods[it.pl];
+        it.valid = true;
+        it.d = points_in(a.n, it.period, a.durations[it.j]);
+        it.stride = 1;
+        const SlideItem si = make_item<T, MEAN>(a, it, VARW);
+        const int64_t i0 = (int64_t)it.tile * kTile;
+        const Best b = block_best(slide_unit_tile<T, VARW, MEAN>(si, i0, x_sh, xw_sh), red);
+        store_best(b, a, it, min((int64_t)kTile, a.n - i0), a.ntiles);
     }
-    if (it.stride != 1) return;
-    const SlideItem si = make_item<T, MEAN>(a, it, VARW);
-    const int64_t i0 = (int64_t)it.tile * kTile;
-    const Best b = block_best(slide_unit_tile<T, VARW, MEAN>(si, i0, x_sh, xw_sh), red);
-    store_best(b, a, it, min((int64_t)kTile, a.n - i0), a.ntiles);
 }
 
-constexpr int kPlanThreads = 1024;
-constexpr int kXcds = 8;                 // MI355X: workgroups go round-robin over 8 XCDs (L2 domains)
 
 // Strided items in queue order: periods are dealt to kXcds queues (pl mod
 // kXcds), each queue lists its periods in order, and each period its
@@ -1452,41 +1437,67 @@ __device__ __forceinline__ void queue_item(int bp, int nd, int64_t idx, int& pl,
     j = nd - 1 - jrev;
 }
 
-// Lists the wave tasks of the strided items of one launch in queue order:
-// toff[idx] is the first task of item idx, toff[bp nd] the total, tmap[task]
-// = idx; queue[kXcds + x] is the first task of XCD queue x (queue[2 kXcds]
-// the total) and queue[x] its pop counter, reset here.
-__global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
-    __shared__ int32_t part[kPlanThreads];
+// Planning of one launch, in three kernels.  k_plan_count: per item, the
+// wave tasks of a strided item (cnt, in queue order) and a flag for an
+// every-offset item (ucnt, in list order: durations longest first, then
+// period).  k_plan_scan (one workgroup): toff[idx] = first task of item idx,
+// toff[bp nd] = total, queue[kXcds + x] = first task of XCD queue x,
+// queue[2 kXcds] = total, queue[2 kXcds + 1] = every-offset items, pop
+// counters reset; and the every-offset list.  k_plan_fill: tmap[task] = item.
+__device__ __forceinline__ void plan_item(const SlideArgs& a, int pl, int j, int& tasks, int& unit) {
+    tasks = 0;
+    unit = 0;
+    const double period = a.periods[pl], dur = a.durations[j];
+    if (!duration_valid(period, dur, a.prm)) return;
+    const int64_t d = points_in(a.n, period, dur);
+    const int64_t st = t0_stride(d, a.prm.dt0);
+    if (st < 2) unit = 1;
+    else tasks = strided_split(a.n, d, st, 64, kTaskMax, a.rmax, a.rcost != 0).ntask;
+}
+
+__global__ __launch_bounds__(256) void k_plan_count(SlideArgs a) {
+    const int64_t items = (int64_t)a.bp * a.nd;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= items) return;
+    int pl, j;
+    queue_item(a.bp, a.nd, idx, pl, j);
+    int tasks, unit;
+    plan_item(a, pl, j, tasks, unit);
+    a.cnt[idx] = tasks;
+    a.ucnt[(int64_t)(a.nd - 1 - j) * a.bp + pl] = unit;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan_scan(SlideArgs a) {
+    __shared__ int32_t part[kPlanThreads], upart[kPlanThreads];
     const int tid = threadIdx.x;
     const int64_t items = (int64_t)a.bp * a.nd;
     const int64_t per = (items + kPlanThreads - 1) / kPlanThreads;
     const int64_t lo = min(items, (int64_t)tid * per), hi = min(items, lo + per);
-    auto count = [&](int64_t idx) -> int {
-        int pl, j;
-        queue_item(a.bp, a.nd, idx, pl, j);
-        const double period = a.periods[pl], dur = a.durations[j];
-        if (!duration_valid(period, dur, a.prm)) return 0;
-        const int64_t d = points_in(a.n, period, dur);
-        const int64_t st = t0_stride(d, a.prm.dt0);
-        return st < 2 ? 0 : strided_split(a.n, d, st, 64, kTaskMax, a.rmax, a.rcost != 0).ntask;
-    };
-    int32_t sum = 0;
-    for (int64_t idx = lo; idx < hi; ++idx) sum += count(idx);
+    int32_t sum = 0, usum = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        sum += a.cnt[i];
+        usum += a.ucnt[i];
+    }
     part[tid] = sum;
+    upart[tid] = usum;
     __syncthreads();
     for (int off = 1; off < kPlanThreads; off <<= 1) {
         const int32_t v = tid >= off ? part[tid - off] : 0;
+        const int32_t uv = tid >= off ? upart[tid - off] : 0;
         __syncthreads();
         part[tid] += v;
+        upart[tid] += uv;
         __syncthreads();
     }
-    int32_t o = part[tid] - sum;
-    for (int64_t idx = lo; idx < hi; ++idx) {
-        const int c = count(idx);
-        a.toff[idx] = o;
-        for (int t = 0; t < c; ++t) a.tmap[o + t] = (int32_t)idx;
-        o += c;
+    int32_t o = part[tid] - sum, uo = upart[tid] - usum;
+    for (int64_t i = lo; i < hi; ++i) {
+        a.toff[i] = o;
+        o += a.cnt[i];
+        if (a.ucnt[i]) {
+            // list order i = jrev bp + pl  ->  item pl nd + j
+            const int32_t jrev = (int32_t)(i / a.bp), pl = (int32_t)(i - (int64_t)jrev * a.bp);
+            a.ulist[uo++] = pl * a.nd + (a.nd - 1 - jrev);
+        }
     }
     if (tid == 0) a.toff[items] = part[kPlanThreads - 1];
     __syncthreads();
@@ -1497,6 +1508,15 @@ __global__ __launch_bounds__(kPlanThreads) void k_strided_plan(SlideArgs a) {
         a.queue[kXcds + tid] = (uint32_t)a.toff[first * a.nd];
     }
     if (tid == kXcds) a.queue[2 * kXcds] = (uint32_t)part[kPlanThreads - 1];
+    if (tid == kXcds + 1) a.queue[2 * kXcds + 1] = (uint32_t)upart[kPlanThreads - 1];
+}
+
+__global__ __launch_bounds__(256) void k_plan_fill(SlideArgs a) {
+    const int64_t items = (int64_t)a.bp * a.nd;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= items) return;
+    const int32_t o = a.toff[idx], c = a.cnt[idx];
+    for (int t = 0; t < c; ++t) a.tmap[o + t] = (int32_t)idx;
 }
 
 // Persistent: every wave pops wave tasks from its XCD's queue, then from the
@@ -1559,11 +1579,13 @@ struct ReduceArgs {
     const double* t;
     int64_t n;
     const double* periods;   // batch-offset
+    const double* durations;
+    gtls_params prm;
     int32_t bp;
     int32_t nd;
     const ItemBest* items;
     int32_t ntiles;
-    const int32_t* toff;     // strided items: task slots, or null
+    const int32_t* toff;     // strided items: task slots
     const ItemBest* sb;
     const uint64_t* keys_a;
     const uint64_t* misc;
@@ -1583,15 +1605,15 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
         const double tmin = from_ordered(a.misc[kTminOrd]);
         double best = -INFINITY, bdepth = 0.0;
         int bj = -1, bi = -1, bd = 0;
+        const double period = a.periods[pl];
         for (int j = 0; j < a.nd; ++j) {
-            const int64_t idx = queue_index(a.bp, a.nd, pl, j);
+            if (!duration_valid(period, a.durations[j], a.prm)) continue;
             const ItemBest* slots = a.items + ((size_t)pl * a.nd + j) * a.ntiles;
-            int nt;
-            if (a.toff && a.toff[idx + 1] > a.toff[idx]) {
+            int nt = a.ntiles;
+            if (t0_stride(points_in(a.n, period, a.durations[j]), a.prm.dt0) >= 2) {
+                const int64_t idx = queue_index(a.bp, a.nd, pl, j);
                 slots = a.sb + a.toff[idx];
                 nt = a.toff[idx + 1] - a.toff[idx];
-            } else {
-                nt = min(max(slots[0].ntiles, 0), a.ntiles);
             }
             for (int t = 0; t < nt; ++t) {
                 const ItemBest b = slots[t];
@@ -1614,7 +1636,6 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
             a.depth[pl] = 0.0;
             a.t0[pl] = NAN;
         } else {
-            const double period = a.periods[pl];
             a.chi2[pl] = chi2_0 - best;
             a.best_dur[pl] = bj;
             a.best_start[pl] = bi;
@@ -2231,7 +2252,8 @@ struct Plan {
     int32_t bp, ntiles;
     bool varw, mean, f32;
     size_t esize, psize;     // bytes per padded-curve element and per prefix element
-    size_t off_a, off_b, off_r, off_w, off_pf, off_items, off_toff, off_tmap, off_sb, off_queue, per_batch;
+    size_t off_a, off_b, off_r, off_w, off_pf, off_items, off_toff, off_tmap, off_sb, off_queue, off_ulist, off_cnt,
+        off_ucnt, per_batch;
 };
 
 Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm, bool varw, size_t budget) {
@@ -2250,7 +2272,8 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     size_t per = 2 * sizeof(uint64_t) * (size_t)n + p.esize * (size_t)p.pstride +
                  (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
                  sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles +
-                 (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kTaskMax + 1024;
+                 (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kTaskMax + 3 * sizeof(int32_t) * (size_t)nd +
+                 1024;
     // Periods per launch: as many as the scratch budget holds, at most
     // 32768.  Fewer, larger launches leave fewer drained tails: on the
     // 3000-day grid, 19 launches instead of 55 (72 GiB against 24 GiB of
@@ -2258,10 +2281,6 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     int64_t bp = (int64_t)(budget / per);
     bp = std::max<int64_t>(1, std::min<int64_t>(bp, 32768));
     bp = std::min<int64_t>(bp, n_periods);
-    // The every-offset slide launches bp * nd * ntiles workgroups of
-    // kSlideThreads: a dispatch counts at most 2^32 - 1 work-items.
-    const int64_t units = std::max<int64_t>(1, (int64_t)nd * p.ntiles);
-    bp = std::max<int64_t>(1, std::min<int64_t>(bp, 0xffffffffLL / (units * kSlideThreads)));
     p.bp = (int32_t)bp;
     size_t o = 0;
     p.off_a = o;
@@ -2283,7 +2302,13 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     p.off_sb = o;
     o = align256(o + sizeof(ItemBest) * (size_t)nd * kTaskMax * bp);
     p.off_queue = o;
-    o = align256(o + (2 * kXcds + 1) * sizeof(uint32_t));
+    o = align256(o + (2 * kXcds + 2) * sizeof(uint32_t));
+    p.off_ulist = o;
+    o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
+    p.off_cnt = o;
+    o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
+    p.off_ucnt = o;
+    o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
     p.per_batch = o;
     return p;
 }
@@ -2291,11 +2316,22 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
 // Unit-stride tiles, then (strided T0 grids) the wave-task list and the
 // persistent strided kernel, sized to fill every CU.
 template <typename T, bool VARW, bool MEAN>
-void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strided, int num_cus, hipStream_t s) {
+void launch_slides(gtls_ctx* ctx, const SlideArgs& la, int64_t units, bool strided, int num_cus, hipStream_t s) {
     {
         StageTimer tm(ctx, kStageSlide);
-        k_slide_unit<T, VARW, MEAN><<<grid, kSlideThreads, 0, s>>>(la);
-        if (strided) k_strided_plan<<<1, kPlanThreads, 0, s>>>(la);
+        const unsigned pgrid = (unsigned)(((int64_t)la.bp * la.nd + 255) / 256);
+        k_plan_count<<<pgrid, 256, 0, s>>>(la);
+        k_plan_scan<<<1, kPlanThreads, 0, s>>>(la);
+        if (strided) k_plan_fill<<<pgrid, 256, 0, s>>>(la);
+        // every-offset work units (list entries x window tiles) by a grid of
+        // at most as many workgroups as are resident at once
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slide_unit<T, VARW, MEAN>, kSlideThreads, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        const unsigned ugrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)per_cu * num_cus));
+        k_slide_unit<T, VARW, MEAN><<<ugrid, kSlideThreads, 0, s>>>(la);
     }
     if (strided) {
         StageTimer tm(ctx, kStageStrided);
@@ -2310,14 +2346,14 @@ void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strid
 }
 
 template <typename T>
-void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strided, bool varw, bool mean,
+void launch_slides(gtls_ctx* ctx, const SlideArgs& la, int64_t units, bool strided, bool varw, bool mean,
                    int num_cus, hipStream_t s) {
     if (varw) {
-        if (mean) launch_slides<T, true, true>(ctx, la, grid, strided, num_cus, s);
-        else launch_slides<T, true, false>(ctx, la, grid, strided, num_cus, s);
+        if (mean) launch_slides<T, true, true>(ctx, la, units, strided, num_cus, s);
+        else launch_slides<T, true, false>(ctx, la, units, strided, num_cus, s);
     } else {
-        if (mean) launch_slides<T, false, true>(ctx, la, grid, strided, num_cus, s);
-        else launch_slides<T, false, false>(ctx, la, grid, strided, num_cus, s);
+        if (mean) launch_slides<T, false, true>(ctx, la, units, strided, num_cus, s);
+        else launch_slides<T, false, false>(ctx, la, units, strided, num_cus, s);
     }
 }
 
@@ -2326,11 +2362,17 @@ void launch_slides(gtls_ctx* ctx, const SlideArgs& la, unsigned grid, bool strid
 hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     hipStream_t s = ctx->stream;
     const int64_t n = a.n;
+    // Scratch regions: the context's grow-only buffers.
+    auto region = [&](DeviceBuffer& b, size_t bytes, char** out) -> hipError_t {
+        const hipError_t e = ensure(ctx, b, bytes);
+        *out = (char*)b.ptr;
+        return e;
+    };
     // Per-curve arrays: misc | w | r | u
     const size_t off_w = 256, off_r = align256(off_w + 8 * (size_t)n), off_u = align256(off_r + 8 * (size_t)n);
-    hipError_t e = ensure(ctx, ctx->curve, align256(off_u + 8 * (size_t)n));
+    char* cb = nullptr;
+    hipError_t e = region(ctx->curve, align256(off_u + 8 * (size_t)n), &cb);
     if (e != hipSuccess) return e;
-    char* cb = (char*)ctx->curve.ptr;
     uint64_t* misc = (uint64_t*)cb;
     double* w = (double*)(cb + off_w);
     double* r = (double*)(cb + off_r);
@@ -2361,11 +2403,12 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     // Template rows for every D in [1, dcap] and the per-D sums.
     const size_t tab_elems = (size_t)trow_off(pl.dcap + 1);
     const size_t off_bsum = align256(pl.esize * tab_elems), off_s1 = align256(off_bsum + 8 * (size_t)(pl.dcap + 1));
-    e = ensure(ctx, ctx->table, align256(off_s1 + 8 * (size_t)(pl.dcap + 1)));
+    char* tb = nullptr;
+    e = region(ctx->table, align256(off_s1 + 8 * (size_t)(pl.dcap + 1)), &tb);
     if (e != hipSuccess) return e;
-    void* table = ctx->table.ptr;
-    double* bsum = (double*)((char*)ctx->table.ptr + off_bsum);
-    double* s1sum = (double*)((char*)ctx->table.ptr + off_s1);
+    void* table = tb;
+    double* bsum = (double*)(tb + off_bsum);
+    double* s1sum = (double*)(tb + off_s1);
     {
         StageTimer tm(ctx, kStagePrep);
         if (pl.f32) k_tmpl_table<float><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, pl.dcap, (float*)table);
@@ -2373,15 +2416,15 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
         if (pl.f32) k_tmpl_sums<float><<<(unsigned)((pl.dcap + 63) / 64), 64, 0, s>>>((const float*)table, pl.dcap, misc, bsum, s1sum);
         else k_tmpl_sums<double><<<(unsigned)((pl.dcap + 63) / 64), 64, 0, s>>>((const double*)table, pl.dcap, misc, bsum, s1sum);
     }
-    e = ensure(ctx, ctx->batch, pl.per_batch);
+    char* bb = nullptr;
+    e = region(ctx->batch, pl.per_batch, &bb);
     while (e == hipErrorOutOfMemory && pl.bp > 1) {
         (void)hipGetLastError();
         budget /= 2;
         pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw, budget);
-        e = ensure(ctx, ctx->batch, pl.per_batch);
+        e = region(ctx->batch, pl.per_batch, &bb);
     }
     if (e != hipSuccess) return e;
-    char* bb = (char*)ctx->batch.ptr;
     uint64_t* keys_a = (uint64_t*)(bb + pl.off_a);
     uint64_t* keys_b = (uint64_t*)(bb + pl.off_b);
     void* rpad = bb + pl.off_r;
@@ -2392,6 +2435,9 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     int32_t* tmap = (int32_t*)(bb + pl.off_tmap);
     ItemBest* sb = (ItemBest*)(bb + pl.off_sb);
     uint32_t* queue = (uint32_t*)(bb + pl.off_queue);
+    int32_t* ulist = (int32_t*)(bb + pl.off_ulist);
+    int32_t* cnt = (int32_t*)(bb + pl.off_cnt);
+    int32_t* ucnt = (int32_t*)(bb + pl.off_ucnt);
     const bool strided = a.prm.dt0 > 0.0;
 
     for (int32_t p0 = 0; p0 < a.n_periods; p0 += pl.bp) {
@@ -2404,11 +2450,11 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
         }
         SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.prm, rpad, wpad, pfx, pl.pstride,
                      misc, table, bsum, s1sum, items, pl.ntiles, toff, tmap, sb, queue, pl.f32 ? 4 : 8,
-                     pl.f32 ? 0 : 1};
-        const unsigned grid = (unsigned)bp * (unsigned)a.n_durations * (unsigned)pl.ntiles;
-        if (pl.f32) launch_slides<float>(ctx, la, grid, strided, varw, pl.mean, ctx->num_cus, s);
-        else launch_slides<double>(ctx, la, grid, strided, varw, pl.mean, ctx->num_cus, s);
-        ReduceArgs ra{a.t, n, a.periods + p0, bp, a.n_durations, items, pl.ntiles, strided ? toff : nullptr, sb,
+                     pl.f32 ? 0 : 1, ulist, cnt, ucnt};
+        const int64_t units = (int64_t)bp * a.n_durations * pl.ntiles;
+        if (pl.f32) launch_slides<float>(ctx, la, units, strided, varw, pl.mean, ctx->num_cus, s);
+        else launch_slides<double>(ctx, la, units, strided, varw, pl.mean, ctx->num_cus, s);
+        ReduceArgs ra{a.t, n, a.periods + p0, a.durations, a.prm, bp, a.n_durations, items, pl.ntiles, toff, sb,
                       keys_a, misc, misc,
                       a.chi2 + p0, a.best_dur + p0, a.best_start + p0, a.depth + p0, a.t0 + p0};
         {
