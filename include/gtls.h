@@ -344,6 +344,36 @@ gtls_status gtls_cnn_get_params(gtls_cnn *net, float *params);
  * bins [B][k], 1 <= k <= 512. */
 gtls_status gtls_cnn_topk(gtls_cnn *net, const float *views, int32_t B, int32_t k, int32_t *bins);
 
+/* Save the network (FP32 parameters, Adam moments and step count) to a file
+ * at path, or load such a file into net (same architecture; the loaded
+ * network continues training exactly where the saved one stopped).
+ * GTLS_EINVAL when the file cannot be written or read, or is not a
+ * checkpoint of this network. */
+gtls_status gtls_cnn_save(gtls_cnn *net, const char *path);
+gtls_status gtls_cnn_load(gtls_cnn *net, const char *path);
+
+/* Search pruned by the learned proposal: the curve's view, the network's k
+ * best of 512 geometric log-period bins over [bin_pmin, bin_pmax] (a period
+ * outside the range counts in the first or last bin), then tls_search on the
+ * grid periods inside those bins.  When that subset is empty or its
+ * periodogram peaks below accept_sde, the whole grid is searched instead
+ * (the fallback, which also gives the full-grid result).
+ *   Arguments as tls_search (host arrays; time non-decreasing, as the view
+ *   needs), net from gtls_cnn_create on the same context, 1 <= k <= 512.
+ *   out: the per-period arrays over the whole grid; periods not searched get
+ *   chi2 NaN, best_dur and best_start -1, depth 0, t0, sr, sde_raw and sde
+ *   NaN.  SR and SDE are those of the searched set, best_period indexes the
+ *   whole grid, n_evals and n_macs count every search made.
+ *   searched [n_periods] (may be NULL): 1 where a period was searched.
+ *   fell_back (may be NULL): 1 when the whole grid was searched.
+ * Synchronous. */
+gtls_status tls_search_pruned(gtls_ctx *ctx, gtls_cnn *net, const double *time, const double *flux,
+                              const double *dy, int64_t n, const double *period_grid,
+                              int32_t n_periods, const double *duration_grid, int32_t n_durations,
+                              const double *tmpl, int32_t n_tmpl, const gtls_params *params,
+                              double bin_pmin, double bin_pmax, int32_t k, double accept_sde,
+                              gtls_result *out, uint8_t *searched, int32_t *fell_back);
+
 /* ---------------- host-side helpers (no device needed) ---------------- */
 
 /* Cubic frequency grid of Sect. 2.2.1 as ascending periods in days.

@@ -517,6 +517,125 @@ gtls_status tls_sde(gtls_ctx* ctx, const double* chi2, int32_t n, int32_t window
     return GTLS_OK;
 }
 
+gtls_status tls_search_pruned(gtls_ctx* ctx, gtls_cnn* net, const double* time, const double* flux, const double* dy,
+                              int64_t n, const double* period_grid, int32_t n_periods, const double* duration_grid,
+                              int32_t n_durations, const double* tmpl, int32_t n_tmpl, const gtls_params* params,
+                              double bin_pmin, double bin_pmax, int32_t k, double accept_sde, gtls_result* out,
+                              uint8_t* searched, int32_t* fell_back) {
+    if (!ctx) return GTLS_EINVAL;
+    if (out) out->best_period = -1;
+    if (!out || !net) return fail(ctx, GTLS_EINVAL, "out and net must not be null");
+    if (k < 1 || k > GTLS_CNN_BINS) return fail(ctx, GTLS_EINVAL, "k must be in [1, 512]");
+    if (!(bin_pmin > 0.0) || !(bin_pmax > bin_pmin) || !std::isfinite(bin_pmax))
+        return fail(ctx, GTLS_EINVAL, "bins need 0 < bin_pmin < bin_pmax");
+    if (!std::isfinite(accept_sde)) return fail(ctx, GTLS_EINVAL, "accept_sde must be finite");
+    if (n_periods < 1 || n < 3 || !time || !flux || !period_grid) return fail(ctx, GTLS_EINVAL, "empty input");
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    const size_t np = (size_t)n_periods;
+    // The network's k best bins for this curve.
+    std::vector<float> view(GTLS_CNN_VIEW);
+    const int64_t off[2] = {0, n};
+    gtls_status st = gtls_cnn_view(ctx, off, time, flux, 1, view.data());
+    if (st != GTLS_OK) return st;
+    std::vector<int32_t> bins((size_t)k);
+    st = gtls_cnn_topk(net, view.data(), 1, k, bins.data());
+    if (st != GTLS_OK) return st;
+    std::vector<uint8_t> chosen(GTLS_CNN_BINS, 0);
+    for (int32_t b : bins) chosen[(size_t)b] = 1;
+    // Grid periods inside the chosen bins (geometric bins over [bin_pmin, bin_pmax]).
+    std::vector<int32_t> idx;
+    const double lr = std::log(bin_pmax / bin_pmin);
+    for (size_t i = 0; i < np; ++i) {
+        double b = std::floor(std::log(period_grid[i] / bin_pmin) / lr * (double)GTLS_CNN_BINS);
+        b = b < 0.0 ? 0.0 : (b > GTLS_CNN_BINS - 1 ? GTLS_CNN_BINS - 1 : b);
+        if (chosen[(size_t)b]) idx.push_back((int32_t)i);
+    }
+    std::vector<double> chi2(np, NAN), depth(np, 0.0), t0(np, NAN), sr(np, NAN), raw(np, NAN), sde(np, NAN);
+    std::vector<int32_t> bd(np, -1), bs(np, -1);
+    int32_t fb = 1;
+    int32_t best = -1;
+    double sde_max = NAN, chi2_null = 0.0;
+    int64_t evals = 0, macs = 0;
+    if (!idx.empty()) {
+        // Search of the subset; accepted when its periodogram peaks at or above accept_sde.
+        const size_t m = idx.size();
+        std::vector<double> per(m), sc(m), sdp(m), st0(m), ssr(m), sraw(m), ssde(m);
+        std::vector<int32_t> sbd(m), sbs(m);
+        for (size_t i = 0; i < m; ++i) per[i] = period_grid[idx[i]];
+        gtls_result r{};
+        r.chi2 = sc.data();
+        r.best_dur = sbd.data();
+        r.best_start = sbs.data();
+        r.depth = sdp.data();
+        r.t0 = st0.data();
+        r.sr = ssr.data();
+        r.sde_raw = sraw.data();
+        r.sde = ssde.data();
+        st = tls_search(ctx, time, flux, dy, n, per.data(), (int32_t)m, duration_grid, n_durations, tmpl, n_tmpl,
+                        &prm, &r);
+        if (st != GTLS_OK) return st;
+        evals = r.n_evals;
+        macs = r.n_macs;
+        chi2_null = r.chi2_null;
+        if (r.sde_max >= accept_sde) {
+            fb = 0;
+            for (size_t i = 0; i < m; ++i) {
+                const size_t g = (size_t)idx[i];
+                chi2[g] = sc[i];
+                bd[g] = sbd[i];
+                bs[g] = sbs[i];
+                depth[g] = sdp[i];
+                t0[g] = st0[i];
+                sr[g] = ssr[i];
+                raw[g] = sraw[i];
+                sde[g] = ssde[i];
+            }
+            best = idx[(size_t)r.best_period];
+            sde_max = r.sde_max;
+        }
+    }
+    if (fb) {
+        // Fallback: the whole grid.
+        gtls_result r{};
+        r.chi2 = chi2.data();
+        r.best_dur = bd.data();
+        r.best_start = bs.data();
+        r.depth = depth.data();
+        r.t0 = t0.data();
+        r.sr = sr.data();
+        r.sde_raw = raw.data();
+        r.sde = sde.data();
+        st = tls_search(ctx, time, flux, dy, n, period_grid, n_periods, duration_grid, n_durations, tmpl, n_tmpl,
+                        &prm, &r);
+        if (st != GTLS_OK) return st;
+        evals += r.n_evals;
+        macs += r.n_macs;
+        chi2_null = r.chi2_null;
+        best = r.best_period;
+        sde_max = r.sde_max;
+    }
+    struct Out { void* dst; const void* src; size_t bytes; } outs[] = {
+        {out->chi2, chi2.data(), 8 * np}, {out->best_dur, bd.data(), 4 * np}, {out->best_start, bs.data(), 4 * np},
+        {out->depth, depth.data(), 8 * np}, {out->t0, t0.data(), 8 * np}, {out->sr, sr.data(), 8 * np},
+        {out->sde_raw, raw.data(), 8 * np}, {out->sde, sde.data(), 8 * np}};
+    for (const Out& o : outs)
+        if (o.dst) std::memcpy(o.dst, o.src, o.bytes);
+    if (searched) {
+        std::memset(searched, fb ? 1 : 0, np);
+        if (!fb)
+            for (int32_t i : idx) searched[i] = 1;
+    }
+    if (fell_back) *fell_back = fb;
+    out->chi2_null = chi2_null;
+    out->best_period = best;
+    out->sde_max = sde_max;
+    out->n_evals = evals;
+    out->n_macs = macs;
+    return GTLS_OK;
+}
+
 gtls_status tls_search_refined(gtls_ctx* ctx, const double* time, const double* flux, const double* dy, int64_t n,
                                const double* period_grid, int32_t n_periods, const double* duration_grid,
                                int32_t n_durations, const double* tmpl, int32_t n_tmpl, const gtls_params* params,

@@ -13,6 +13,9 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "gtls.h"
@@ -757,6 +760,74 @@ gtls_status gtls_cnn_topk(gtls_cnn* net, const float* views, int32_t B, int32_t 
     if (e == hipSuccess) e = hipMemcpyAsync(bins, net->bins, 4 * (size_t)B * k, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? GTLS_OK : cnn_fail(net, e, "cnn topk");
+}
+
+// Checkpoint file: 8-byte magic "GTLSCNN1", int64 parameter count, int64
+// Adam step, then the FP32 parameters, the Adam first and second moments
+// (little-endian, parameter order).
+static const char kCkptMagic[8] = {'G', 'T', 'L', 'S', 'C', 'N', 'N', '1'};
+
+gtls_status gtls_cnn_save(gtls_cnn* net, const char* path) {
+    if (!net || !path) return GTLS_EINVAL;
+    std::vector<float> buf(3 * (size_t)kNParams);
+    hipStream_t s = net->ctx->stream;
+    hipError_t e = hipMemcpyAsync(buf.data(), net->params, 4 * (size_t)kNParams, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(buf.data() + kNParams, net->adam_m, 4 * (size_t)kNParams, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(buf.data() + 2 * kNParams, net->adam_v, 4 * (size_t)kNParams, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cnn_fail(net, e, "cnn save");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) {
+        net->ctx->err = std::string("cannot open ") + path + " for writing";
+        return GTLS_EINVAL;
+    }
+    const int64_t hdr[2] = {kNParams, net->step};
+    bool ok = std::fwrite(kCkptMagic, 1, 8, f) == 8 && std::fwrite(hdr, 8, 2, f) == 2 &&
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) {
+        net->ctx->err = std::string("write to ") + path + " failed";
+        return GTLS_EINVAL;
+    }
+    return GTLS_OK;
+}
+
+gtls_status gtls_cnn_load(gtls_cnn* net, const char* path) {
+    if (!net || !path) return GTLS_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) {
+        net->ctx->err = std::string("cannot open ") + path;
+        return GTLS_EINVAL;
+    }
+    char magic[8];
+    int64_t hdr[2];
+    std::vector<float> buf(3 * (size_t)kNParams);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kCkptMagic, 8) == 0 &&
+              std::fread(hdr, 8, 2, f) == 2 && hdr[0] == kNParams && hdr[1] >= 0 &&
+              std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;
+    std::fclose(f);
+    if (!ok) {
+        net->ctx->err = std::string(path) + " is not a checkpoint of this network";
+        return GTLS_EINVAL;
+    }
+    hipStream_t s = net->ctx->stream;
+    hipError_t e = hipMemcpyAsync(net->params, buf.data(), 4 * (size_t)kNParams, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(net->adam_m, buf.data() + kNParams, 4 * (size_t)kNParams, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(net->adam_v, buf.data() + 2 * kNParams, 4 * (size_t)kNParams, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        k_pack_weights<<<(C * C * KW + 255) / 256, 256, 0, s>>>(net->params, net->wf, net->wb);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cnn_fail(net, e, "cnn load");
+    net->step = hdr[1];
+    return GTLS_OK;
 }
 
 }  // extern "C"

@@ -27,7 +27,7 @@ EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_defau
             "tls_sde", "tls_search_refined", "tls_transit_stats", "gtls_period_grid_ofir",
             "gtls_duration_grid", "gtls_template_quadratic", "gtls_cnn_num_params", "gtls_cnn_create",
             "gtls_cnn_destroy", "gtls_cnn_view", "gtls_cnn_forward", "gtls_cnn_gradients", "gtls_cnn_train_step",
-            "gtls_cnn_get_params", "gtls_cnn_topk"]
+            "gtls_cnn_get_params", "gtls_cnn_topk", "gtls_cnn_save", "gtls_cnn_load", "tls_search_pruned"]
 CNN_VIEW, CNN_BINS = 4096, 512
 
 
@@ -190,6 +190,16 @@ def lib():
         L.gtls_cnn_get_params.argtypes = [vp, fp]
         L.gtls_cnn_topk.restype = ctypes.c_int
         L.gtls_cnn_topk.argtypes = [vp, fp, ctypes.c_int32, ctypes.c_int32, _ip]
+        L.gtls_cnn_save.restype = ctypes.c_int
+        L.gtls_cnn_save.argtypes = [vp, ctypes.c_char_p]
+        L.gtls_cnn_load.restype = ctypes.c_int
+        L.gtls_cnn_load.argtypes = [vp, ctypes.c_char_p]
+        L.tls_search_pruned.restype = ctypes.c_int
+        L.tls_search_pruned.argtypes = [vp, vp, _dp, _dp, _dp, ctypes.c_int64, _dp, ctypes.c_int32, _dp,
+                                        ctypes.c_int32, _dp, ctypes.c_int32, ctypes.POINTER(gtls_params),
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.POINTER(gtls_result), ctypes.POINTER(ctypes.c_uint8),
+                                        ctypes.POINTER(ctypes.c_int32)]
         L.gtls_template_quadratic.restype = ctypes.c_int
         L.gtls_template_quadratic.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int32, _dp]
         _lib = L
@@ -541,3 +551,37 @@ def gtls_cnn_topk(net: Cnn, views, k: int) -> np.ndarray:
     out = np.empty((len(v), int(k)), dtype=np.int32)
     _check(lib().gtls_cnn_topk(net.ptr, _fp(v), len(v), int(k), out.ctypes.data_as(_ip)), net.ctx.ptr)
     return out
+
+
+def gtls_cnn_save(net: Cnn, path: str):
+    _check(lib().gtls_cnn_save(net.ptr, os.fsencode(path)), net.ctx.ptr)
+
+
+def gtls_cnn_load(net: Cnn, path: str):
+    _check(lib().gtls_cnn_load(net.ptr, os.fsencode(path)), net.ctx.ptr)
+
+
+def tls_search_pruned(ctx: Context, net: Cnn, time, flux, dy, period_grid, duration_grid, tmpl, bin_pmin: float,
+                      bin_pmax: float, k: int, accept_sde: float, params: gtls_params | None = None):
+    """Learned-proposal search; returns (SearchResult, searched mask, fell_back)."""
+    t, y, e = _f64(time), _f64(flux), _f64(dy)
+    per, dur, tm = _f64(period_grid), _f64(duration_grid), _f64(tmpl)
+    npd = len(per)
+    out = {k_: np.empty(npd) for k_ in ("chi2", "depth", "t0", "sr", "sde_raw", "sde")}
+    out["best_dur"] = np.empty(npd, dtype=np.int32)
+    out["best_start"] = np.empty(npd, dtype=np.int32)
+    searched = np.zeros(npd, dtype=np.uint8)
+    fell = ctypes.c_int32(0)
+    res = gtls_result()
+    for k_ in ("chi2", "depth", "t0", "sr", "sde_raw", "sde"):
+        setattr(res, k_, _p(out[k_]))
+    res.best_dur = out["best_dur"].ctypes.data_as(_ip)
+    res.best_start = out["best_start"].ctypes.data_as(_ip)
+    prm = params if params is not None else gtls_params_default()
+    _check(lib().tls_search_pruned(ctx.ptr, net.ptr, _p(t), _p(y), _p(e), len(t), _p(per), npd, _p(dur), len(dur),
+                                   _p(tm), len(tm), ctypes.byref(prm), float(bin_pmin), float(bin_pmax), int(k),
+                                   float(accept_sde), ctypes.byref(res),
+                                   searched.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(fell)),
+           ctx.ptr)
+    return (SearchResult(chi2_null=res.chi2_null, best_period=res.best_period, sde_max=res.sde_max,
+                         n_evals=res.n_evals, n_macs=res.n_macs, **out), searched.astype(bool), bool(fell.value))

@@ -143,3 +143,74 @@ def test_training_reduces_loss_and_topk(ctx):
     q = gtls.gtls_cnn_get_params(net)
     assert np.all(np.isfinite(q)) and not np.array_equal(q, p)
     net.close()
+
+
+def test_checkpoint_resume_is_bit_exact(ctx, tmp_path):
+    """Train 5 steps, save, train 4 more; a new network loaded from the
+    checkpoint and trained the same 4 steps ends with the same parameters,
+    bit for bit (parameters, Adam moments and step count are restored)."""
+    p = synth.cnn_init(41).astype(np.float32)
+    g = synth.rng(42)
+    batches = [(g.normal(0, 1, (4, cnn.L)).astype(np.float32), g.integers(0, cnn.NB, 4).astype(np.int32))
+               for _ in range(9)]
+    net = gtls.Cnn(ctx, p)
+    for v, lab in batches[:5]:
+        gtls.gtls_cnn_train_step(net, v, lab, lr=2e-3)
+    path = str(tmp_path / "net.ckpt")
+    gtls.gtls_cnn_save(net, path)
+    saved = gtls.gtls_cnn_get_params(net)
+    for v, lab in batches[5:]:
+        gtls.gtls_cnn_train_step(net, v, lab, lr=2e-3)
+    a = gtls.gtls_cnn_get_params(net)
+    net.close()
+    other = gtls.Cnn(ctx, synth.cnn_init(99).astype(np.float32))
+    gtls.gtls_cnn_load(other, path)
+    assert np.array_equal(gtls.gtls_cnn_get_params(other), saved)
+    for v, lab in batches[5:]:
+        gtls.gtls_cnn_train_step(other, v, lab, lr=2e-3)
+    b = gtls.gtls_cnn_get_params(other)
+    assert np.array_equal(a, b)
+    with open(path, "r+b") as f:                       # a damaged header is refused
+        f.write(b"XXXX")
+    with pytest.raises(gtls.GtlsError):
+        gtls.gtls_cnn_load(other, path)
+    other.close()
+
+
+def test_pruned_search_subset_and_fallback(ctx, oracle):
+    """tls_search_pruned: the periods it searches are exactly the grid
+    periods inside the network's top-k bins; their chi2, windows and depths
+    equal the plain search's at those periods (periods are independent), the
+    SR/SDE equal the oracle's periodogram of that subset; with an accept
+    threshold no subset can reach, the result is the whole-grid search."""
+    c = synth.curve_random(71, n=3000, inject=True)
+    span = c["t"].max() - c["t"].min()
+    grid = gtls.gtls_period_grid_ofir(span, 2.0, pmin_days=0.5, pmax_days=span / 2)
+    durs = gtls.gtls_duration_grid(grid[0], grid[-1], 10)
+    tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.02, 0.0, 256)
+    net = gtls.Cnn(ctx, synth.cnn_init(5).astype(np.float32))
+    full = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], grid, durs, tm)
+    k = 48
+    res, searched, fell = gtls.tls_search_pruned(ctx, net, c["t"], c["y"], c["dy"], grid, durs, tm, grid[0],
+                                                 grid[-1], k, -1e300)
+    assert not fell
+    view = gtls.gtls_cnn_view(ctx, np.array([0, len(c["t"])]), c["t"], c["y"])
+    top = gtls.gtls_cnn_topk(net, view, k)[0]
+    b = np.clip(np.floor(np.log(grid / grid[0]) / np.log(grid[-1] / grid[0]) * 512), 0, 511).astype(int)
+    assert np.array_equal(searched, np.isin(b, top))
+    sel = np.nonzero(searched)[0]
+    assert len(sel) > 0
+    assert np.array_equal(res.chi2[sel], full.chi2[sel])
+    assert np.array_equal(res.best_start[sel], full.best_start[sel])
+    assert np.array_equal(res.depth[sel], full.depth[sel])
+    assert np.all(np.isnan(res.chi2[~searched])) and np.all(res.best_dur[~searched] == -1)
+    sr, raw, sde, best = oracle.sde(full.chi2[sel], 91)
+    assert np.allclose(res.sde[sel], sde, rtol=0, atol=1e-9 * np.max(np.abs(sde)))
+    assert res.best_period == sel[best]
+    assert res.n_evals > 0
+    res2, searched2, fell2 = gtls.tls_search_pruned(ctx, net, c["t"], c["y"], c["dy"], grid, durs, tm, grid[0],
+                                                    grid[-1], k, 1e300)
+    assert fell2 and np.all(searched2)
+    assert np.array_equal(res2.chi2, full.chi2) and res2.best_period == full.best_period
+    assert res2.n_evals == res.n_evals + full.n_evals
+    net.close()
