@@ -54,10 +54,24 @@ def workload(name: str):
     return c, periods, durs, tm
 
 
+def host_threads():
+    """Threads the oracle baseline uses: every core this process may run on
+    (its CPU affinity), capped by OMP_NUM_THREADS when that is set (the GPU
+    hosts give one GPU's job a fixed share of their cores that way)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        avail = min(avail, int(cap))
+    return max(1, avail)
+
+
 def cpu_baseline(c, periods, durs, tm, prm, n_sample: int, seed: int = 0):
     """The oracle, as it stands, on a seeded sample of the workload's periods."""
     from oracle import oracle as O
-    threads = min(16, os.cpu_count() or 1)
+    threads = host_threads()
     g = np.random.Generator(np.random.PCG64(seed))
     idx = np.sort(g.choice(len(periods), size=min(n_sample, len(periods)), replace=False))
     t0 = time.perf_counter()
@@ -65,9 +79,16 @@ def cpu_baseline(c, periods, durs, tm, prm, n_sample: int, seed: int = 0):
                      k_min=prm.k_min, k_max=prm.k_max, q_cap=prm.q_cap, depth_mode=prm.depth_mode,
                      threads=threads)
     el = time.perf_counter() - t0
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
     return {"value": r.n_evals / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "affinity_cores": affinity,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
             "sample": f"{len(idx)} of {len(periods)} periods (seeded uniform sample), same curve, durations "
-                      f"and dt0; {r.n_evals} windows in {el:.1f} s"}
+                      f"and dt0; {r.n_evals} windows in {el:.1f} s on {threads} threads (all cores this "
+                      f"process may use, capped by OMP_NUM_THREADS)"}
 
 
 def survey_bench(args):

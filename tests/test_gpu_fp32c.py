@@ -2,22 +2,24 @@
 residuals, template and correlation blocks FP32 flushed into FP64; moving-
 average prefix sums Kahan-compensated FP32) against the FP64 oracle.
 
-Bar: chi2 within rtol 1e-5; best period identical; per-period best window
-identical, or else a certified near-tie: the oracle's literal chi2 at the
-window the GPU chose lies within the same tolerance of the oracle's minimum.
-Each test prints the errors it measured.
+Bar (tests/fp32c_bound.py): chi2 within rtol 1e-5; best period identical;
+per-period best window identical, or else a certified near-tie, never at the
+best period: the oracle's Delta chi2 at the window the GPU chose falls short
+of its maximum by no more than the FP32C error bound of the two windows.
+Each test prints the errors it measured.  The full 3000-day and TESS-like
+grids are compared in test_gpu_fullgrid.py.
 """
 import os
 
 import numpy as np
 import pytest
 
+from fp32c_bound import check_fp32c
 from paper_2607_00348_amd import gtls, synth
 
 pytestmark = pytest.mark.gpu
 
 THREADS = min(16, os.cpu_count() or 1)
-RTOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -27,28 +29,10 @@ def ctx():
     c.close()
 
 
-def _check(oracle, c, periods, durs, tm, res, ref, label, idx=None):
-    idx = np.arange(len(periods)) if idx is None else idx
-    chi2 = res.chi2[idx]
-    rel = np.abs(chi2 - ref.chi2) / ref.chi2
-    assert np.max(rel) <= RTOL, (label, float(np.max(rel)))
-    same = (res.best_dur[idx] == ref.best_dur) & (res.best_start[idx] == ref.best_start)
-    n_tie = 0
-    for k in np.nonzero(~same)[0]:
-        p = periods[idx[k]]
-        j = int(res.best_dur[idx[k]])
-        d = oracle.points_in_duration(len(c["t"]), p, durs[j])
-        s = oracle.resample(tm, d)
-        perm = oracle.fold_sort(c["t"], p)
-        lit = oracle.chi2_literal(c["y"], c["dy"], perm, int(res.best_start[idx[k]]), d, s,
-                                  float(res.depth[idx[k]]))
-        assert abs(lit - ref.chi2[k]) <= RTOL * ref.chi2[k], (label, k, lit, ref.chi2[k])
-        n_tie += 1
-    dep = ref.depth > 0
-    drel = np.abs(res.depth[idx][dep & same] - ref.depth[dep & same]) / ref.depth[dep & same]
-    print(f"{label}: periods {len(idx)}, max chi2 rel err {np.max(rel):.2e}, "
-          f"max depth rel err {np.max(drel) if drel.size else 0:.2e}, near-tie windows {n_tie}", flush=True)
-    return n_tie
+def _check(oracle, c, periods, durs, tm, res, ref, label, depth_mode=0):
+    fx = {"chi2": ref.chi2, "best_dur": ref.best_dur, "best_start": ref.best_start, "chi2_null": ref.chi2_null,
+          "n_evals": ref.n_evals}
+    check_fp32c(oracle, c, periods, durs, tm, res, fx, label, depth_mode)
 
 
 @pytest.mark.parametrize("seed,n,kw", [
@@ -73,9 +57,7 @@ def test_fp32c_random_curves(ctx, oracle, seed, n, kw):
     res = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, prm)
     ref = oracle.tls_search(c["t"], c["y"], c["dy"], periods, durs, tm, dt0=prm.dt0, depth_mode=prm.depth_mode,
                             threads=THREADS)
-    _check(oracle, c, periods, durs, tm, res, ref, f"seed {seed}")
-    assert res.best_period == oracle.sde(ref.chi2)[3]
-    assert res.n_evals == ref.n_evals
+    _check(oracle, c, periods, durs, tm, res, ref, f"seed {seed}", prm.depth_mode)
 
 
 def test_fp32c_kepler_90d(ctx, oracle):
@@ -89,7 +71,6 @@ def test_fp32c_kepler_90d(ctx, oracle):
     res = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, prm)
     ref = oracle.tls_search(c["t"], c["y"], c["dy"], periods, durs, tm, threads=THREADS)
     _check(oracle, c, periods, durs, tm, res, ref, "kepler_90d fp32c")
-    assert res.best_period == oracle.sde(ref.chi2)[3]
 
 
 def test_fp32c_tess_precision_stress(ctx, oracle):
@@ -108,24 +89,3 @@ def test_fp32c_tess_precision_stress(ctx, oracle):
     res = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods[idx], durs, tm, prm)
     ref = oracle.tls_search(c["t"], c["y"], c["dy"], periods[idx], durs, tm, threads=THREADS)
     _check(oracle, c, periods[idx], durs, tm, res, ref, "tess fp32c")
-
-
-def test_fp32c_full_3000d_grid_evaluates_every_window(ctx):
-    """Regression test of the launch split at full size: the 3000-day curve's
-    whole grid at T0 step 0.1 (the largest launches the library makes, whose
-    every-offset grid must stay within one dispatch's work-item count) must
-    evaluate exactly the windows the FP64 search evaluates, and agree with it
-    within the FP32C tolerance."""
-    c = synth.curve_3000d()
-    span = c["t"][-1] - c["t"][0]
-    periods = gtls.gtls_period_grid_ofir(span, 3.0, pmin_days=0.5, pmax_days=1500.0)
-    durs = gtls.gtls_duration_grid(0.5, 1500.0, 20)
-    tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
-    print("fp32c vs fp64, full 3000-day grid", len(periods), flush=True)
-    r32 = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm,
-                          gtls.gtls_params_default(dt0=0.1, precision=gtls.GTLS_FP32C))
-    r64 = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, gtls.gtls_params_default(dt0=0.1))
-    assert r32.n_evals == r64.n_evals and r32.n_macs == r64.n_macs
-    err = np.max(np.abs(r32.chi2 - r64.chi2) / r64.chi2)
-    print(f"max rel chi2 error {err:.2e}", flush=True)
-    assert err < RTOL and r32.best_period == r64.best_period
