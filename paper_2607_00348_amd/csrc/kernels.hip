@@ -2,20 +2,23 @@
 //
 // Per trial period P (Sect. 2.3 of the GTLS paper):
 //   k_fold_sort   one 1024-thread workgroup per period: phase fold on raw
-//                 times (Sect. 2.3.1), 32-bit fixed-point phase keys, a
-//                 4-pass stable LSD radix sort with wave-ballot ranking, a
-//                 tie-fix of equal keys by full FP64 phase then input index,
-//                 then the cyclic padding (Sect. 2.3.2): the folded weights
-//                 and residuals gathered in phase order for n + D_max
-//                 positions, and (moving-average depth only) exact integer
-//                 prefix sums of 1 - y over the padded curve (Sect. 2.3.3).
-//   k_slide       one 256-thread workgroup per (period, duration): the
-//                 transit template resampled to D points is slid over the
-//                 padded curve (Sect. 2.3.4, in-transit term); each lane owns
-//                 16 consecutive windows whose correlation sums run in
-//                 registers over a padded, bank-conflict-free LDS tile.  The
-//                 per-window depth and chi2 improvement are reduced to the
-//                 first best window.
+//                 times (Sect. 2.3.1), 24-bit fixed-point phase keys, a
+//                 3-pass stable LSD radix sort (8-bit digits) with wave-ballot
+//                 ranking, a tie-fix of equal keys by full FP64 phase then
+//                 input index, then the cyclic padding (Sect. 2.3.2): the
+//                 folded residuals (and weights) gathered in phase order for
+//                 n + D_max positions, and (moving-average depth only) exact
+//                 integer prefix sums of 1 - y over the padded curve
+//                 (Sect. 2.3.3).
+//   k_plan_*      per launch: the every-offset items and the wave tasks of
+//                 the items with a T0 step of two or more points.
+//   k_slide_unit  every T0 offset (Sect. 2.3.4, in-transit term): work units
+//                 of 4096 windows of one (period, duration) item; each lane
+//                 owns 16 consecutive windows whose correlation sums run in
+//                 registers over a padded, bank-conflict-free LDS tile.
+//   k_slide_strided  T0 step s >= 2 (Sect. 2.5): persistent waves pop wave
+//                 tasks; each lane owns R windows s points apart and streams
+//                 its run of the padded curve once for all of them.
 //   k_reduce      per period: first best over durations -> chi2(P), depth, T0.
 //   k_sde_*       SR, SDE_raw, running-median detrend, argmax (Sect. 2.4).
 //

@@ -172,30 +172,6 @@ def _compare_rows(res, ref, idx, label):
     assert np.allclose(res.t0[idx], ref.t0, rtol=RTOL, atol=0), label
 
 
-def test_kepler_3000d_full_grid_sampled(ctx, oracle):
-    """The 3000-day workload over its whole Ofir grid (418,590 periods,
-    20 durations) at dt0 = 0.1; the oracle recomputes a seeded sample of
-    periods plus the neighbourhood of the injected and the best period."""
-    c = synth.curve_3000d()
-    span = c["t"][-1] - c["t"][0]
-    periods = oracle.period_grid_ofir(span, 3.0, pmin_days=0.5, pmax_days=1500.0)
-    durs = oracle.duration_grid(0.5, 1500.0, 20)
-    tm = oracle.template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
-    _say("kepler_3000d full grid dt0=0.1", len(periods), len(c["t"]))
-    res, prm = _search_both(ctx, c, periods, durs, tm, dt0=0.1)
-    inj = int(np.argmin(np.abs(periods - 365.0)))
-    g = synth.rng(77)
-    idx = np.unique(np.r_[g.choice(len(periods), 40, replace=False), inj - 2, inj - 1, inj, inj + 1, inj + 2,
-                          res.best_period, 0, len(periods) - 1])
-    ref = _sampled(oracle, c, periods, durs, tm, idx, dt0=0.1)
-    _compare_rows(res, ref, idx, "kepler_3000d")
-    assert abs(periods[res.best_period] / 365.0 - 1) < 0.01
-    # periodogram statistics at full size, from the GPU chi2 (properties)
-    sr = res.chi2.min() / res.chi2
-    assert np.array_equal(res.sr, sr)
-    assert np.argmax(res.sde) == res.best_period
-
-
 def test_kepler_3000d_every_offset_subset(ctx, oracle):
     """Every T0 offset on the 3000-day curve, for a seeded subset of its
     grid (periods are independent, so a subset is an exact slice)."""
