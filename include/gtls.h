@@ -180,6 +180,31 @@ gtls_status tls_search_dev(gtls_ctx *ctx, const double *time, const double *flux
                            int32_t *best_start, double *depth, double *t0, double *sr,
                            double *sde_raw, double *sde, gtls_summary *summary);
 
+/* tls_search_dev without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, outputs and results are those of
+ * tls_search_dev.  Every scratch region (per-point arrays, template rows,
+ * the sort and padding of each launch's periods, the SR array when sr is
+ * NULL) comes from one static device array of 256 MiB that the library holds
+ * on each GPU it runs on until the process ends; no hipMalloc, hipFree or
+ * allocating library routine is called.  Limit: the per-curve arrays
+ * (24 B per point), the template rows for every D up to q_cap n (about
+ * 4 (q_cap n)^2 bytes in FP64, half in FP32C) and at least one period's sort
+ * and padding (about 24 B per point) must fit in the 256 MiB, i.e. curves of
+ * up to about 50,000 points at q_cap = 0.15 in FP64; larger calls return
+ * GTLS_ENOMEM and leave the outputs unwritten.  Profiling must be off
+ * (GTLS_EINVAL).
+ * All calls on one GPU share its array: calls that overlap in time on one
+ * GPU (several host threads, or several streams without ordering) race and
+ * give undefined results; calls ordered on one stream are safe. */
+gtls_status tls_search_dev_noalloc(gtls_ctx *ctx, const double *time, const double *flux,
+                                   const double *dy, int64_t n, const double *period_grid,
+                                   int32_t n_periods, const double *duration_grid,
+                                   int32_t n_durations, const double *tmpl, int32_t n_tmpl,
+                                   const gtls_params *params, double *chi2, int32_t *best_dur,
+                                   int32_t *best_start, double *depth, double *t0, double *sr,
+                                   double *sde_raw, double *sde, gtls_summary *summary);
+
 /* Batched survey: many light curves searched in one persistent launch over
  * (curve, period) work items (Sect. 2.3-2.4 per curve); with
  * params->batch_route_min > 0, curves of at least that many points are

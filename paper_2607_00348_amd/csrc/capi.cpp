@@ -113,6 +113,11 @@ gtls_status gtls_create(gtls_ctx** out, int device, void* hip_stream) {
     gtls_ctx* ctx = new gtls_ctx();
     ctx->device = device;
     ctx->num_cus = prop.multiProcessorCount;     // sizes the persistent kernels
+    e = gtls::static_scratch_address(device, &ctx->static_scratch);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, GTLS_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(e));
+    }
     if (hip_stream) {
         ctx->stream = (hipStream_t)hip_stream;
     } else {
@@ -204,6 +209,49 @@ gtls_status tls_search_dev(gtls_ctx* ctx, const double* time, const double* flux
     gtls::SearchArgs a{time, flux, dy, n, period_grid, n_periods, duration_grid, n_durations, tmpl, n_tmpl, prm,
                        chi2, best_dur, best_start, depth, t0, srp, sde_raw, sde, summary};
     e = gtls::run_search(ctx, a);
+    if (e != hipSuccess) return hip_fail(ctx, e, "search");
+    return GTLS_OK;
+}
+
+gtls_status tls_search_dev_noalloc(gtls_ctx* ctx, const double* time, const double* flux, const double* dy, int64_t n,
+                           const double* period_grid, int32_t n_periods, const double* duration_grid,
+                           int32_t n_durations, const double* tmpl, int32_t n_tmpl, const gtls_params* params,
+                           double* chi2, int32_t* best_dur, int32_t* best_start, double* depth, double* t0,
+                           double* sr, double* sde_raw, double* sde, gtls_summary* summary) {
+    if (!ctx) return GTLS_EINVAL;
+    gtls_params prm;
+    if (params) prm = *params;
+    else gtls_params_default(&prm);
+    gtls_status st = check_sizes(ctx, n, n_periods, n_durations, n_tmpl);
+    if (st != GTLS_OK) return st;
+    if ((st = check_params(ctx, prm)) != GTLS_OK) return st;
+    if (!time || !flux || !dy || !period_grid || !duration_grid || !tmpl || !chi2 || !best_dur || !best_start ||
+        !depth || !t0 || !sde_raw || !sde || !summary)
+        return fail(ctx, GTLS_EINVAL, "null device pointer");
+    if (ctx->profiling) return fail(ctx, GTLS_EINVAL, "profiling is on (it creates HIP events); turn it off");
+    if (!ctx->static_scratch) return fail(ctx, GTLS_EDEVICE, "static scratch unavailable on this device");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set device");
+    // Every scratch region comes from the static array; SR too when the
+    // caller passes none.
+    char* base = ctx->static_scratch;
+    size_t bytes = gtls::kStaticScratchBytes;
+    double* srp = sr;
+    if (!srp) {
+        const size_t b = align256(sizeof(double) * (size_t)n_periods);
+        if (b >= bytes) return fail(ctx, GTLS_ENOMEM, "n_periods too large for the static scratch");
+        srp = (double*)base;
+        base += b;
+        bytes -= b;
+    }
+    gtls::SearchArgs a{time, flux, dy, n, period_grid, n_periods, duration_grid, n_durations, tmpl, n_tmpl, prm,
+                       chi2, best_dur, best_start, depth, t0, srp, sde_raw, sde, summary, base, bytes};
+    e = gtls::run_search(ctx, a);
+    if (e == hipErrorOutOfMemory)
+        return fail(ctx, GTLS_ENOMEM,
+                    "curve too large for the static scratch of " + std::to_string(gtls::kStaticScratchBytes >> 20) +
+                        " MiB (per-curve arrays, template rows up to q_cap n points and one period's sort and "
+                        "padding must fit)");
     if (e != hipSuccess) return hip_fail(ctx, e, "search");
     return GTLS_OK;
 }

@@ -47,6 +47,10 @@ struct SearchArgs {
     double* sde_raw;
     double* sde;
     gtls_summary* summary;
+    // Allocation-free calls: every scratch region is carved from this
+    // device buffer of fixed_bytes instead of the context's own buffers.
+    char* fixed = nullptr;
+    size_t fixed_bytes = 0;
 };
 
 struct DeviceBuffer {
@@ -103,6 +107,9 @@ struct gtls_ctx {
     gtls::DeviceBuffer bscratch; // batched: per-workgroup sort/padding scratch
     gtls::BatchCache bcache;
     int num_cus = 0;
+    // Device address of the library's static scratch array on this context's
+    // device (resolved once per device at context creation).
+    char* static_scratch = nullptr;
     // per-stage timing (gtls_profile_enable / gtls_profile_read)
     bool profiling = false;
     double prof_ms[8] = {0};
@@ -129,6 +136,10 @@ hipError_t run_sde(gtls_ctx* ctx, const double* chi2_dev, int32_t n, int32_t win
                    double* raw_dev, double* sde_dev, gtls_summary* summary_dev);
 hipError_t ensure(gtls_ctx* ctx, DeviceBuffer& b, size_t bytes);
 hipError_t run_search_batch(gtls_ctx* ctx, const BatchArgsHost& a);
+// Address of the static scratch array on `device` (which must be current),
+// resolved with hipGetSymbolAddress on the first call for that device.
+hipError_t static_scratch_address(int device, char** ptr);
+extern const size_t kStaticScratchBytes;
 hipError_t profile_collect(gtls_ctx* ctx);
 
 enum Stage { kStagePrep = 0, kStageSort = 1, kStageSlide = 2, kStageReduce = 3, kStageSde = 4, kStageStrided = 5 };

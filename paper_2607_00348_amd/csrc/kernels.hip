@@ -37,6 +37,14 @@
 
 #include "gtls_impl.hpp"
 
+#include <mutex>
+
+// Scratch of the allocation-free search entry point (tls_search_dev_noalloc):
+// one array per GPU, alive until the process ends.  Host code never passes
+// this name to a kernel: it uses the device address resolved per device by
+// gtls::static_scratch_address.
+static __device__ __align__(256) char scratch[(size_t)256 << 20];
+
 namespace gtls {
 namespace {
 
@@ -2193,6 +2201,24 @@ hipError_t ensure(gtls_ctx* ctx, DeviceBuffer& b, size_t bytes) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+const size_t kStaticScratchBytes = sizeof(scratch);
+
+hipError_t static_scratch_address(int device, char** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static char* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (char*)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
 static hipEvent_t pool_event(gtls_ctx* ctx) {
     if (!ctx->event_pool.empty()) {
         hipEvent_t e = ctx->event_pool.back();
@@ -2365,8 +2391,16 @@ void launch_slides(gtls_ctx* ctx, const SlideArgs& la, int64_t units, bool strid
 hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     hipStream_t s = ctx->stream;
     const int64_t n = a.n;
-    // Scratch regions: the context's grow-only buffers.
+    // Scratch regions: the context's grow-only buffers, or consecutive
+    // pieces of the caller-provided fixed buffer (no allocation).
+    size_t fixed_used = 0;
     auto region = [&](DeviceBuffer& b, size_t bytes, char** out) -> hipError_t {
+        if (a.fixed) {
+            if (fixed_used + align256(bytes) > a.fixed_bytes) return hipErrorOutOfMemory;
+            *out = a.fixed + fixed_used;
+            fixed_used += align256(bytes);
+            return hipSuccess;
+        }
         const hipError_t e = ensure(ctx, b, bytes);
         *out = (char*)b.ptr;
         return e;
@@ -2397,7 +2431,7 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     // the device has free beside the context's current period scratch; on
     // an allocation failure the budget halves and the plan is redone.
     size_t budget = (size_t)72 << 30;
-    {
+    if (!a.fixed) {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
             budget = std::min(budget, (free_b + ctx->batch.bytes) / 2);
@@ -2412,6 +2446,11 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     void* table = tb;
     double* bsum = (double*)(tb + off_bsum);
     double* s1sum = (double*)(tb + off_s1);
+    if (a.fixed) {
+        // periods per launch: whatever the rest of the fixed buffer holds
+        if (fixed_used >= a.fixed_bytes) return hipErrorOutOfMemory;
+        pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw, a.fixed_bytes - fixed_used);
+    }
     {
         StageTimer tm(ctx, kStagePrep);
         if (pl.f32) k_tmpl_table<float><<<(unsigned)pl.dcap, 256, 0, s>>>(a.tmpl, a.n_tmpl, pl.dcap, (float*)table);
@@ -2421,7 +2460,7 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     }
     char* bb = nullptr;
     e = region(ctx->batch, pl.per_batch, &bb);
-    while (e == hipErrorOutOfMemory && pl.bp > 1) {
+    while (!a.fixed && e == hipErrorOutOfMemory && pl.bp > 1) {
         (void)hipGetLastError();
         budget /= 2;
         pl = make_plan(n, a.n_periods, a.n_durations, a.prm, varw, budget);

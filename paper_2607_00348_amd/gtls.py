@@ -23,7 +23,7 @@ GTLS_DEPTH_WLS, GTLS_DEPTH_MEAN = 0, 1
 
 EXPORTED = ["gtls_create", "gtls_destroy", "gtls_last_error", "gtls_params_default", "gtls_sync",
             "gtls_profile_enable", "gtls_profile_read",
-            "tls_search", "tls_search_dev", "tls_search_batch", "tls_search_batch_dev", "tls_fold_sort",
+            "tls_search", "tls_search_dev", "tls_search_dev_noalloc", "tls_search_batch", "tls_search_batch_dev", "tls_fold_sort",
             "tls_sde", "tls_search_refined", "tls_transit_stats", "gtls_period_grid_ofir",
             "gtls_duration_grid", "gtls_template_quadratic", "gtls_cnn_num_params", "gtls_cnn_create",
             "gtls_cnn_destroy", "gtls_cnn_view", "gtls_cnn_forward", "gtls_cnn_gradients", "gtls_cnn_train_step",
@@ -143,6 +143,8 @@ def lib():
         L.tls_search_dev.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, ctypes.c_int32,
                                      vp, ctypes.c_int32, ctypes.POINTER(gtls_params), vp, vp, vp, vp, vp, vp,
                                      vp, vp, vp]
+        L.tls_search_dev_noalloc.restype = ctypes.c_int
+        L.tls_search_dev_noalloc.argtypes = L.tls_search_dev.argtypes
         lp = ctypes.POINTER(ctypes.c_int64)
         L.tls_search_batch.restype = ctypes.c_int
         L.tls_search_batch.argtypes = [vp, lp, _dp, _dp, _dp, ctypes.c_int32, lp, _dp, _dp, ctypes.c_int32, _dp,
@@ -341,6 +343,18 @@ def tls_search_dev(ctx: Context, time, flux, dy, n: int, period_grid, n_periods:
                                 v(duration_grid), int(n_durations), v(tmpl), int(n_tmpl), ctypes.byref(prm),
                                 v(chi2), v(best_dur), v(best_start), v(depth), v(t0), v(sr), v(sde_raw), v(sde),
                                 v(summary)), ctx.ptr)
+
+
+def tls_search_dev_noalloc(ctx: Context, time, flux, dy, n: int, period_grid, n_periods: int, duration_grid,
+                           n_durations: int, tmpl, n_tmpl: int, params: gtls_params | None, chi2, best_dur,
+                           best_start, depth, t0, sr, sde_raw, sde, summary):
+    """tls_search_dev with no device allocation (the library's static scratch)."""
+    prm = params if params is not None else gtls_params_default()
+    v = ctypes.c_void_p
+    _check(lib().tls_search_dev_noalloc(ctx.ptr, v(time), v(flux), v(dy), int(n), v(period_grid), int(n_periods),
+                                        v(duration_grid), int(n_durations), v(tmpl), int(n_tmpl), ctypes.byref(prm),
+                                        v(chi2), v(best_dur), v(best_start), v(depth), v(t0), v(sr), v(sde_raw),
+                                        v(sde), v(summary)), ctx.ptr)
 
 
 @dataclass
