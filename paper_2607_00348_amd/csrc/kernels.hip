@@ -759,17 +759,20 @@ struct SlideArgs {
     const double* s1sum;     // [D] template sums
     ItemBest* items;         // [bp][nd][ntiles]
     int32_t ntiles;          // window tiles per unit-stride item
-    // Strided items: wave tasks in launch order.
-    int32_t* toff;           // [bp nd + 1] first task of item (jrev bp + pl); last = total
-    int32_t* tmap;           // [bp nd kTaskMax] item of task
-    ItemBest* sb;            // [bp nd kTaskMax] best of task
+    // Strided items: row tasks (16 lanes each) packed four to a wave task.
+    int32_t* toff;           // [bp nd] first row slot of item (queue index)
+    int32_t* tcnt;           // [bp nd] row slots of item (0: not strided)
+    int32_t* rowmap;         // [row slots] item of the slot (queue index), -1: empty
+    int32_t* wfirst;         // [waves] first row slot of the wave task
+    int32_t* cell_s;         // [cells + 1] planner: row slots per cell, then their exclusive scan
+    int32_t* cell_w;         // [cells + 1] planner: wave tasks per cell, then their exclusive scan
+    ItemBest* sb;            // [row slots] best of each row
     uint32_t* queue;         // [2 kXcds + 2] pop counters, queue starts, total, unit-item count
     int32_t rmax;            // most windows per lane (the FP32C rule keeps it at 4)
     int32_t rcost;           // 1: windows per lane by the wave-chunk count (FP64), 0: the FP32C rule
     // Every-offset items (stride 1), listed by the planner: item pl nd + j,
     // longest durations first, then period.
     int32_t* ulist;          // [bp nd]
-    int32_t* cnt;            // [bp nd] planner scratch: tasks per item in queue order
     int32_t* ucnt;           // [bp nd] planner scratch: 1 per every-offset item in list order
 };
 
@@ -992,7 +995,6 @@ __device__ Best slide_unit_tile(const SlideItem& si, int64_t i0, T* x_sh, T* xw_
 // takes it with template point j - r s.  The lane walks j upward over its
 // own contiguous run of the padded curve in chunks of 16 points.
 constexpr int kSC = 16;                             // j steps per chunk
-constexpr int kTaskMax = 16;                        // wave tasks per strided item
 constexpr int kRunCap = 1024;                       // FP32C rule: (R - 1) s + 32 <= kRunCap
 
 // Windows per lane for FP32C, the rule the single-curve and batched searches
@@ -1323,6 +1325,225 @@ __device__ Best strided_windows_coop_r(int R, const SlideItem& si, int64_t m_lo,
     }
 }
 
+// ------------------------------------------------------------------------
+// Row-packed strided slide (single-curve search).  A wave is four rows of 16
+// lanes; each row works on windows of one strided item (period, duration),
+// so four small items (the same duration at four neighbouring periods of an
+// XCD's list) share a wave instead of leaving most of its lanes idle, while
+// an item with many windows fills all four rows itself.  Within a row the
+// template points are broadcast from a lane of the row (DPP row broadcast),
+// so each row follows its own item's stride and duration.  The wave's loop
+// runs over the longest run of its rows; a shorter row meets template zeros
+// past its run, which leaves its sums unchanged.
+constexpr int kRowLanes = 16;
+constexpr int kRowMax = 64;          // rows per strided item
+constexpr int kCellItems = 4;        // neighbouring periods whose rows share waves
+
+struct RowItem {
+    const void* rp;                  // T padded residuals of the row's period
+    const void* wp;                  // T padded weights (varying weights only)
+    const void* pf;                  // prefix sums (moving-average depth only)
+    const void* trow;                // T template row of D
+    int64_t D, s, limit;             // points, T0 step, end of the padded curve
+    int64_t m_lo, m_hi;              // windows of this pass
+    double bconst, s1;
+    bool active;                     // the row has windows in this pass
+};
+
+template <typename V>
+__device__ __forceinline__ V pick4(int k, V v0, V v1, V v2, V v3) {
+    return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
+}
+
+// Windows [m_lo, m_hi) of each active row on one wave, R windows per lane
+// (lane l of row k owns windows m_lo + l R .. + R - 1, s points apart);
+// returns the lane's first best over its windows, merged into `best`.
+template <typename T, bool VARW, bool MEAN, int R>
+__device__ void strided_rows(const RowItem (&ri)[4], Best& best, int64_t& evals, T* stage, T* stage_w) {
+    constexpr int P = kPiece<T>;
+    constexpr int NP = kSC / P;                     // pieces per run chunk = load instructions per chunk
+    constexpr int OPI = 64 / NP;                    // runs per load instruction
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 4, lp = lane & 15;
+    const int a = lane / NP, q = lane % NP;
+    // this lane's row
+    const bool act = pick4(row, ri[0].active, ri[1].active, ri[2].active, ri[3].active);
+    const int64_t s = pick4(row, ri[0].s, ri[1].s, ri[2].s, ri[3].s);
+    const int64_t D = pick4(row, ri[0].D, ri[1].D, ri[2].D, ri[3].D);
+    const int64_t m_lo = pick4(row, ri[0].m_lo, ri[1].m_lo, ri[2].m_lo, ri[3].m_lo);
+    const int64_t m_hi = pick4(row, ri[0].m_hi, ri[1].m_hi, ri[2].m_hi, ri[3].m_hi);
+    const T* __restrict__ tbase = (const T*)pick4(row, ri[0].trow, ri[1].trow, ri[2].trow, ri[3].trow) - 2 * kSC;
+    const uint32_t tl = (uint32_t)(lane & 15) * 2 * sizeof(T);
+    T* const srow = stage + lane * kStRow<T>;
+    T* const srow_w = VARW ? stage_w + lane * kStRow<T> : nullptr;
+    // the longest run over the active rows (a row with no windows in this
+    // pass loads the first active row's curve and contributes nothing)
+    int64_t J = 0;
+    int first = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (ri[k].active) {
+            J = max(J, ri[k].D + (int64_t)(R - 1) * ri[k].s);
+            if (first < 0) first = k;
+        }
+    const int64_t nch = (J + kSC - 1) / kSC;
+
+    struct TPair {
+        T lo, hi;
+    };
+    auto tload = [&](int64_t c0, TPair (&tv)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t klo = c0 - (int64_t)r * s;
+            const int64_t kc = klo <= -2 * kSC ? -2 * kSC : (klo >= D ? D : klo);
+            tv[r] = load_at<TPair>(tbase, (uint32_t)(kc + 2 * kSC) * (uint32_t)sizeof(T) + tl);
+        }
+    };
+    auto stage_get = [&](const T* rowp, T (&x)[kSC]) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const Piece<T> pc = *reinterpret_cast<const Piece<T>*>(rowp + i * P);
+#pragma unroll
+            for (int e = 0; e < P; ++e) x[i * P + e] = pc.v[e];
+        }
+    };
+    auto products = [&](auto hc, double (&acc)[R], double (&bacc)[VARW ? R : 1], const T (&x)[kSC],
+                        const T (&xw)[VARW ? kSC : 1], const TPair (&tv)[R]) {
+        constexpr int H = decltype(hc)::value;
+        T tlo[R], thi[R], qlo[VARW ? R : 1], qhi[VARW ? R : 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            tlo[r] = tv[r].lo;
+            thi[r] = tv[r].hi;
+            if constexpr (VARW) {
+                qlo[r] = tv[r].lo * tv[r].lo;
+                qhi[r] = tv[r].hi * tv[r].hi;
+            }
+        }
+        if constexpr (sizeof(T) == 8) {
+            dpp_chunk<T, R, H>(acc, tlo, thi, x, std::make_integer_sequence<int, kSC>{});
+            if constexpr (VARW) dpp_chunk<T, R, H>(bacc, qlo, qhi, xw, std::make_integer_sequence<int, kSC>{});
+        } else {
+            T ca[R], cq[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) ca[r] = cq[r] = (T)0;
+            dpp_chunk<T, R, H>(ca, tlo, thi, x, std::make_integer_sequence<int, kSC>{});
+            if constexpr (VARW) dpp_chunk<T, R, H>(cq, qlo, qhi, xw, std::make_integer_sequence<int, kSC>{});
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r] += (double)ca[r];
+                if constexpr (VARW) bacc[r] += (double)cq[r];
+            }
+        }
+    };
+
+    // Loader pieces: piece i of this lane belongs to run o = i OPI + a, whose
+    // row o / 16 = i OPI / 16 is the same for every lane of the wave.
+    const T* rbase[NP];
+    const T* wbase[VARW ? NP : 1];
+    uint32_t cb[NP], cend[NP];
+    const void* frp = pick4(first, ri[0].rp, ri[1].rp, ri[2].rp, ri[3].rp);
+    const void* fwp = pick4(first, ri[0].wp, ri[1].wp, ri[2].wp, ri[3].wp);
+    const int64_t flimit = pick4(first, ri[0].limit, ri[1].limit, ri[2].limit, ri[3].limit);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int k = (i * OPI) >> 4;             // the same for every lane once unrolled
+        const bool ka = ri[k].active;
+        rbase[i] = (const T*)(ka ? ri[k].rp : frp);
+        if constexpr (VARW) wbase[i] = (const T*)(ka ? ri[k].wp : fwp);
+        const int lo = (i * OPI + a) & 15;        // owner's lane in its row
+        const int64_t mrun = ka ? min(ri[k].m_lo + (int64_t)lo * R, ri[k].m_hi - 1) : 0;
+        cb[i] = (uint32_t)((mrun * (ka ? ri[k].s : 0) + q * P) * (int64_t)sizeof(T));
+        cend[i] = (uint32_t)((ka ? ri[k].limit : flimit) * (int64_t)sizeof(T));
+    }
+    auto xload = [&](bool w, int64_t c0, Piece<T> (&nx)[NP]) {
+        const uint32_t co = (uint32_t)c0 * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) nx[i] = load_at<Piece<T>>(w ? wbase[VARW ? i : 0] : rbase[i], min(cb[i] + co, cend[i]));
+    };
+    auto stage_put = [&](T* buf, const Piece<T> (&nx)[NP]) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) *reinterpret_cast<Piece<T>*>(buf + (i * OPI + a) * kStRow<T> + q * P) = nx[i];
+    };
+    auto restage = [&](Piece<T> (&nx)[NP], Piece<T> (&nw)[VARW ? NP : 1], T (&x)[kSC], T (&xw)[VARW ? kSC : 1]) {
+        wave_sync();
+        stage_put(stage, nx);
+        if constexpr (VARW) stage_put(stage_w, nw);
+        wave_sync();
+        stage_get(srow, x);
+        if constexpr (VARW) stage_get(srow_w, xw);
+    };
+
+    double acc[R], bacc[VARW ? R : 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < (VARW ? R : 1); ++r) bacc[r] = 0.0;
+    T x[2][kSC], xw[2][VARW ? kSC : 1];
+    TPair tv[2][R];
+    Piece<T> nx[NP], nw[VARW ? NP : 1];
+    auto pieces = [&](int64_t j) {
+        xload(false, j * kSC, nx);
+        if constexpr (VARW) xload(true, j * kSC, nw);
+    };
+    pieces(0);
+    tload(0, tv[0]);
+    tload(2 * kSC, tv[1]);
+    restage(nx, nw, x[0], xw[0]);
+    pieces(1);
+    auto pair = [&](auto slotc, int64_t j) {
+        constexpr int sl = decltype(slotc)::value;
+        restage(nx, nw, x[1], xw[1]);
+        pieces(j + 2);
+        products(std::integral_constant<int, 0>{}, acc, bacc, x[0], xw[0], tv[sl]);
+        restage(nx, nw, x[0], xw[0]);
+        pieces(j + 3);
+        products(std::integral_constant<int, 1>{}, acc, bacc, x[1], xw[1], tv[sl]);
+        tload((j + 4) * kSC, tv[sl]);
+    };
+    const int64_t npair = (nch + 1) / 2;
+    int64_t c = 0;
+    for (; c + 2 <= npair; c += 2) {
+        pair(std::integral_constant<int, 0>{}, 2 * c);
+        pair(std::integral_constant<int, 1>{}, 2 * c + 2);
+    }
+    if (c < npair) pair(std::integral_constant<int, 0>{}, 2 * c);
+    if (act) {
+        const void* pf = pick4(row, ri[0].pf, ri[1].pf, ri[2].pf, ri[3].pf);
+        const double bconst = pick4(row, ri[0].bconst, ri[1].bconst, ri[2].bconst, ri[3].bconst);
+        const double s1 = pick4(row, ri[0].s1, ri[1].s1, ri[2].s1, ri[3].s1);
+        const int64_t ml = m_lo + (int64_t)lp * R;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t m = ml + r;
+            if (m < m_hi) {
+                const int64_t i = m * s;
+                double dchi2, depth;
+                fit<MEAN>(acc[r], VARW ? bacc[r] : bconst, window_deficit<T, MEAN>(pf, i, D), s1, dchi2, depth);
+                consider(best, dchi2, depth, i);
+                ++evals;
+            }
+        }
+    }
+}
+
+// First-best over the 16 lanes of each row (largest dchi2, then smallest
+// start), returned to every lane of the row.
+__device__ __forceinline__ Best row_best(Best best) {
+    for (int off = 8; off > 0; off >>= 1) {
+        const double od = __shfl_xor(best.dchi2, off);
+        const double op = __shfl_xor(best.depth, off);
+        const long long oi = __shfl_xor((long long)best.start, off);
+        const bool take = (od > best.dchi2) || (od == best.dchi2 && oi >= 0 && (best.start < 0 || oi < best.start));
+        if (take) {
+            best.dchi2 = od;
+            best.depth = op;
+            best.start = oi;
+        }
+    }
+    return best;
+}
+
 // Windows per lane for the cooperative strided slide (FP64, where the sums do
 // not depend on it): R = 4 or 8, whichever needs fewer wave-chunks,
 // waves(R) * chunks(R) = ceil(ceil(nw / R) / 64) * ceil((D + (R - 1) s) / 16);
@@ -1346,7 +1567,7 @@ __host__ __device__ __forceinline__ int strided_r_cost(int64_t nw, int64_t s, in
 }
 
 // Wave tasks of a strided item: its window groups (64 R windows each) split
-// into at most kTaskMax contiguous runs.
+// into at most max_tasks contiguous runs.
 struct StridedSplit {
     int R;
     int64_t nw, groups;
@@ -1448,22 +1669,125 @@ __device__ __forceinline__ void queue_item(int bp, int nd, int64_t idx, int& pl,
     j = nd - 1 - jrev;
 }
 
-// Planning of one launch, in three kernels.  k_plan_count: per item, the
-// wave tasks of a strided item (cnt, in queue order) and a flag for an
-// every-offset item (ucnt, in list order: durations longest first, then
-// period).  k_plan_scan (one workgroup): toff[idx] = first task of item idx,
-// toff[bp nd] = total, queue[kXcds + x] = first task of XCD queue x,
-// queue[2 kXcds] = total, queue[2 kXcds + 1] = every-offset items, pop
-// counters reset; and the every-offset list.  k_plan_fill: tmap[task] = item.
-__device__ __forceinline__ void plan_item(const SlideArgs& a, int pl, int j, int& tasks, int& unit) {
-    tasks = 0;
-    unit = 0;
-    const double period = a.periods[pl], dur = a.durations[j];
-    if (!duration_valid(period, dur, a.prm)) return;
-    const int64_t d = points_in(a.n, period, dur);
-    const int64_t st = t0_stride(d, a.prm.dt0);
-    if (st < 2) unit = 1;
-    else tasks = strided_split(a.n, d, st, 64, kTaskMax, a.rmax, a.rcost != 0).ntask;
+// Planning of one launch.
+//  - Every-offset items (T0 step 1) are listed for k_slide_unit.
+//  - Strided items are cut into row tasks: rows of 16 lanes with R windows
+//    per lane, at most kRowMax rows per item (a row then takes several
+//    consecutive groups of 16 R windows).  Rows are packed four to a wave
+//    task within a cell: one duration at kCellItems neighbouring periods of
+//    one XCD's list, consecutive items with the same R sharing waves.  Cells
+//    are queued per XCD (the XCD's periods in order, blocks of kCellItems,
+//    durations longest first), so an XCD works on a few periods at a time.
+// k_plan_count (items): every-offset flags.  k_rplan_count (cells): row
+// slots and wave tasks per cell.  k_plan_scan (one workgroup): the
+// every-offset list, the cell scans and the XCD queue bounds
+// (queue[kXcds + x] first wave task of XCD x, queue[2 kXcds] total,
+// queue[2 kXcds + 1] every-offset items, pop counters reset).
+// k_rplan_fill (cells): toff, tcnt, rowmap and wfirst.
+
+// FP64 windows per lane for row tasks: R = 4 or 8, whichever needs fewer
+// row-chunks, rows(R) x chunks(R) = ceil(ceil(nw / R) / 16) x
+// ceil((D + (R - 1) s) / 16); ties go to R = 4.
+__host__ __device__ __forceinline__ int strided_r_rows(int64_t nw, int64_t s, int64_t d) {
+    int best_r = 4;
+    int64_t best = -1;
+    for (int r = 4; r <= 8; r *= 2) {
+        const int64_t lanes = (nw + r - 1) / r;
+        const int64_t cost = ((lanes + kRowLanes - 1) / kRowLanes) * ((d + (r - 1) * s + kSC - 1) / kSC);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_r = r;
+        }
+    }
+    return best_r;
+}
+
+__device__ __forceinline__ int64_t xcd_blocks(int bp, int x) {
+    return (xcd_periods(bp, x) + kCellItems - 1) / kCellItems;
+}
+
+__device__ __forceinline__ int64_t cell_first(int bp, int nd, int x) {
+    int64_t c = 0;
+    for (int y = 0; y < x; ++y) c += xcd_blocks(bp, y) * nd;
+    return c;
+}
+
+__device__ __forceinline__ int64_t cell_count(int bp, int nd) { return cell_first(bp, nd, kXcds); }
+
+struct CellItem {
+    int32_t idx;             // queue index of the item, -1: no period here
+    bool strided;
+    int R, rows;
+};
+
+struct CellPlan {
+    CellItem it[kCellItems];
+    int nsub;
+    int sub_k0[kCellItems], sub_k1[kCellItems];  // items [k0, k1) of each subgroup (strided ones count)
+    int sub_rows[kCellItems], sub_waves[kCellItems];
+    int slots, waves;
+};
+
+// Row tasks of a strided item: windows per lane, windows, groups of
+// 16 R windows, rows.
+__device__ __forceinline__ void item_rows(const SlideArgs& a, int64_t d, int64_t st, int& R, int64_t& nw,
+                                          int64_t& groups, int& rows) {
+    nw = (a.n + st - 1) / st;
+    R = a.rcost ? strided_r_rows(nw, st, d) : strided_r(nw, st, d, 64, a.rmax);
+    groups = ((nw + R - 1) / R + kRowLanes - 1) / kRowLanes;
+    rows = (int)min(groups, (int64_t)kRowMax);
+}
+
+__device__ void plan_cell(const SlideArgs& a, int64_t c, CellPlan& cp) {
+    int x = 0;
+    int64_t cx = c;
+    for (; x < kXcds - 1; ++x) {
+        const int64_t cc = xcd_blocks(a.bp, x) * a.nd;
+        if (cx < cc) break;
+        cx -= cc;
+    }
+    const int64_t b = cx / a.nd;
+    const int j = a.nd - 1 - (int)(cx - b * a.nd);
+    const int64_t npx = xcd_periods(a.bp, x);
+    for (int k = 0; k < kCellItems; ++k) {
+        CellItem& it = cp.it[k];
+        it.idx = -1;
+        it.strided = false;
+        it.R = 0;
+        it.rows = 0;
+        const int64_t i = b * kCellItems + k;
+        if (i >= npx) continue;
+        const int pl = (int)(x + kXcds * i);
+        it.idx = (int32_t)queue_index(a.bp, a.nd, pl, j);
+        const double period = a.periods[pl], dur = a.durations[j];
+        if (!duration_valid(period, dur, a.prm)) continue;
+        const int64_t d = points_in(a.n, period, dur);
+        const int64_t st = t0_stride(d, a.prm.dt0);
+        if (st < 2) continue;
+        int64_t nw, groups;
+        it.strided = true;
+        item_rows(a, d, st, it.R, nw, groups, it.rows);
+    }
+    cp.nsub = 0;
+    cp.slots = 0;
+    cp.waves = 0;
+    int prev_r = 0;
+    for (int k = 0; k < kCellItems; ++k) {
+        if (!cp.it[k].strided) continue;
+        if (cp.it[k].R != prev_r) {
+            cp.sub_k0[cp.nsub] = k;
+            cp.sub_rows[cp.nsub] = 0;
+            ++cp.nsub;
+            prev_r = cp.it[k].R;
+        }
+        cp.sub_k1[cp.nsub - 1] = k + 1;
+        cp.sub_rows[cp.nsub - 1] += cp.it[k].rows;
+    }
+    for (int g = 0; g < cp.nsub; ++g) {
+        cp.sub_waves[g] = (cp.sub_rows[g] + 3) / 4;
+        cp.slots += 4 * cp.sub_waves[g];
+        cp.waves += cp.sub_waves[g];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_plan_count(SlideArgs a) {
@@ -1472,111 +1796,229 @@ __global__ __launch_bounds__(256) void k_plan_count(SlideArgs a) {
     if (idx >= items) return;
     int pl, j;
     queue_item(a.bp, a.nd, idx, pl, j);
-    int tasks, unit;
-    plan_item(a, pl, j, tasks, unit);
-    a.cnt[idx] = tasks;
+    const double period = a.periods[pl], dur = a.durations[j];
+    int unit = 0;
+    if (duration_valid(period, dur, a.prm)) unit = t0_stride(points_in(a.n, period, dur), a.prm.dt0) < 2;
     a.ucnt[(int64_t)(a.nd - 1 - j) * a.bp + pl] = unit;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void k_plan_scan(SlideArgs a) {
-    __shared__ int32_t part[kPlanThreads], upart[kPlanThreads];
-    const int tid = threadIdx.x;
-    const int64_t items = (int64_t)a.bp * a.nd;
-    const int64_t per = (items + kPlanThreads - 1) / kPlanThreads;
-    const int64_t lo = min(items, (int64_t)tid * per), hi = min(items, lo + per);
-    int32_t sum = 0, usum = 0;
-    for (int64_t i = lo; i < hi; ++i) {
-        sum += a.cnt[i];
-        usum += a.ucnt[i];
-    }
-    part[tid] = sum;
-    upart[tid] = usum;
-    __syncthreads();
-    for (int off = 1; off < kPlanThreads; off <<= 1) {
-        const int32_t v = tid >= off ? part[tid - off] : 0;
-        const int32_t uv = tid >= off ? upart[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        upart[tid] += uv;
-        __syncthreads();
-    }
-    int32_t o = part[tid] - sum, uo = upart[tid] - usum;
-    for (int64_t i = lo; i < hi; ++i) {
-        a.toff[i] = o;
-        o += a.cnt[i];
-        if (a.ucnt[i]) {
-            // list order i = jrev bp + pl  ->  item pl nd + j
-            const int32_t jrev = (int32_t)(i / a.bp), pl = (int32_t)(i - (int64_t)jrev * a.bp);
-            a.ulist[uo++] = pl * a.nd + (a.nd - 1 - jrev);
-        }
-    }
-    if (tid == 0) a.toff[items] = part[kPlanThreads - 1];
-    __syncthreads();
-    if (tid < kXcds) {
-        int64_t first = 0;
-        for (int y = 0; y < tid; ++y) first += xcd_periods(a.bp, y);
-        a.queue[tid] = 0u;
-        a.queue[kXcds + tid] = (uint32_t)a.toff[first * a.nd];
-    }
-    if (tid == kXcds) a.queue[2 * kXcds] = (uint32_t)part[kPlanThreads - 1];
-    if (tid == kXcds + 1) a.queue[2 * kXcds + 1] = (uint32_t)upart[kPlanThreads - 1];
+__global__ __launch_bounds__(256) void k_rplan_count(SlideArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cell_count(a.bp, a.nd)) return;
+    CellPlan cp;
+    plan_cell(a, c, cp);
+    a.cell_s[c] = cp.slots;
+    a.cell_w[c] = cp.waves;
 }
 
-__global__ __launch_bounds__(256) void k_plan_fill(SlideArgs a) {
+// In-place exclusive scan of v[0 .. m) by one workgroup, v[m] = total.
+__device__ void block_scan(int32_t* v, int64_t m, int32_t* part) {
+    const int tid = threadIdx.x;
+    const int64_t per = (m + kPlanThreads - 1) / kPlanThreads;
+    const int64_t lo = min(m, (int64_t)tid * per), hi = min(m, lo + per);
+    int32_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += v[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kPlanThreads; off <<= 1) {
+        const int32_t o = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += o;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int32_t c = v[i];
+        v[i] = run;
+        run += c;
+    }
+    if (tid == kPlanThreads - 1) v[m] = part[kPlanThreads - 1];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan_scan(SlideArgs a) {
+    __shared__ int32_t part[kPlanThreads];
+    const int tid = threadIdx.x;
     const int64_t items = (int64_t)a.bp * a.nd;
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= items) return;
-    const int32_t o = a.toff[idx], c = a.cnt[idx];
-    for (int t = 0; t < c; ++t) a.tmap[o + t] = (int32_t)idx;
+    // the every-offset list (list order jrev bp + pl -> item pl nd + j)
+    {
+        const int64_t per = (items + kPlanThreads - 1) / kPlanThreads;
+        const int64_t lo = min(items, (int64_t)tid * per), hi = min(items, lo + per);
+        int32_t usum = 0;
+        for (int64_t i = lo; i < hi; ++i) usum += a.ucnt[i];
+        part[tid] = usum;
+        __syncthreads();
+        for (int off = 1; off < kPlanThreads; off <<= 1) {
+            const int32_t o = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += o;
+            __syncthreads();
+        }
+        int32_t uo = part[tid] - usum;
+        for (int64_t i = lo; i < hi; ++i)
+            if (a.ucnt[i]) {
+                const int32_t jrev = (int32_t)(i / a.bp), pl = (int32_t)(i - (int64_t)jrev * a.bp);
+                a.ulist[uo++] = pl * a.nd + (a.nd - 1 - jrev);
+            }
+        if (tid == 0) a.queue[2 * kXcds + 1] = (uint32_t)part[kPlanThreads - 1];
+        __syncthreads();
+    }
+    const int64_t cells = cell_count(a.bp, a.nd);
+    block_scan(a.cell_s, cells, part);
+    block_scan(a.cell_w, cells, part);
+    if (tid < kXcds) {
+        a.queue[tid] = 0u;
+        a.queue[kXcds + tid] = (uint32_t)a.cell_w[cell_first(a.bp, a.nd, tid)];
+    }
+    if (tid == kXcds) a.queue[2 * kXcds] = (uint32_t)a.cell_w[cells];
+}
+
+__global__ __launch_bounds__(256) void k_rplan_fill(SlideArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cell_count(a.bp, a.nd)) return;
+    CellPlan cp;
+    plan_cell(a, c, cp);
+    for (int k = 0; k < kCellItems; ++k)
+        if (cp.it[k].idx >= 0 && !cp.it[k].strided) {
+            a.toff[cp.it[k].idx] = 0;
+            a.tcnt[cp.it[k].idx] = 0;
+        }
+    int32_t slot = a.cell_s[c], wave = a.cell_w[c];
+    for (int g = 0; g < cp.nsub; ++g) {
+        int32_t r = 0;
+        for (int k = cp.sub_k0[g]; k < cp.sub_k1[g]; ++k) {
+            const CellItem& it = cp.it[k];
+            if (!it.strided) continue;
+            a.toff[it.idx] = slot + r;
+            a.tcnt[it.idx] = it.rows;
+            for (int t = 0; t < it.rows; ++t) a.rowmap[slot + r + t] = it.idx;
+            r += it.rows;
+        }
+        for (; r < 4 * cp.sub_waves[g]; ++r) a.rowmap[slot + r] = -1;
+        for (int w = 0; w < cp.sub_waves[g]; ++w) a.wfirst[wave + w] = slot + 4 * w;
+        slot += 4 * cp.sub_waves[g];
+        wave += cp.sub_waves[g];
+    }
+}
+
+template <typename T, bool VARW, bool MEAN>
+__device__ __forceinline__ void strided_rows_r(int R, const RowItem (&ri)[4], Best& best, int64_t& evals, T* stage,
+                                               T* stage_w) {
+    if constexpr (sizeof(T) == 8) {
+        if (R == 8) strided_rows<T, VARW, MEAN, 8>(ri, best, evals, stage, stage_w);
+        else strided_rows<T, VARW, MEAN, 4>(ri, best, evals, stage, stage_w);
+    } else {
+        switch (R) {
+            case 4: strided_rows<T, VARW, MEAN, 4>(ri, best, evals, stage, stage_w); break;
+            case 2: strided_rows<T, VARW, MEAN, 2>(ri, best, evals, stage, stage_w); break;
+            default: strided_rows<T, VARW, MEAN, 1>(ri, best, evals, stage, stage_w); break;
+        }
+    }
 }
 
 // Persistent: every wave pops wave tasks from its XCD's queue, then from the
-// others, until all are exhausted.
-// Two waves per SIMD for constant weights (what the loop needs fits the 256
-// registers that allow it; a few task-level values spill); per-point weights
-// double the staged operands, so they keep one wave per SIMD and use the
-// accumulation registers too.
+// others, until all are exhausted.  A wave task is four row slots; each
+// non-empty one is a row of an item (its rows split the item's groups of
+// 16 R windows evenly).  Two waves per SIMD for constant weights; per-point
+// weights double the staged operands and keep one.
 template <typename T, bool VARW, bool MEAN>
-__global__ __launch_bounds__(kSlideThreads, VARW ? 1 : 2) void k_slide_strided(SlideArgs a) {
+__global__ __launch_bounds__(kSlideThreads, VARW ? 1 : 2) void k_slide_rows(SlideArgs a) {
     __shared__ __align__(16) T stages[(kSlideThreads / 64) * (VARW ? 2 : 1) * kStage<T>];
     const int lane = threadIdx.x & 63;
+    const int row = lane >> 4;
     T* stage = stages + (threadIdx.x >> 6) * (VARW ? 2 : 1) * kStage<T>;
     T* stage_w = VARW ? stage + kStage<T> : nullptr;
+    const size_t pfs = sizeof(T) == 8 ? sizeof(__int128) : sizeof(float2);
     const int x0 = (int)(blockIdx.x % kXcds);
-    for (int k = 0; k < kXcds; ++k) {
-        const int x = (x0 + k) % kXcds;
+    for (int xk = 0; xk < kXcds; ++xk) {
+        const int x = (x0 + xk) % kXcds;
         const uint32_t qb = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.queue[kXcds + x]);
         const uint32_t qe = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.queue[kXcds + x + 1]);
         for (;;) {
             // Every lane takes part in the pop (lane 0 adds 1, the rest 0) so
             // no divergent branch feeds the broadcast of lane 0's ticket.
             const uint32_t ticket = atomicAdd(&a.queue[x], lane == 0 ? 1u : 0u);
-            const uint32_t task = qb + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
-            if (task >= qe) break;
-            const int32_t idx = __builtin_amdgcn_readfirstlane(a.tmap[task]);
-            const int t = (int)task - __builtin_amdgcn_readfirstlane(a.toff[idx]);
-            ItemInfo it;
-            int pl, j;
-            queue_item(a.bp, a.nd, idx, pl, j);
-            it.pl = pl;
-            it.j = j;
-            it.tile = 0;
-            it.valid = true;
-            it.period = a.periods[it.pl];
-            it.d = points_in(a.n, it.period, a.durations[it.j]);
-            it.stride = t0_stride(it.d, a.prm.dt0);
-            const SlideItem si = make_item<T, MEAN>(a, it, VARW);
-            const StridedSplit sp = strided_split(a.n, it.d, it.stride, 64, kTaskMax, a.rmax, a.rcost != 0);
-            int64_t m_lo, m_hi;
-            strided_task_range(sp, t, m_lo, m_hi);
-            const Best b = strided_windows_coop_r<T, VARW, MEAN>(sp.R, si, m_lo, m_hi, stage, stage_w);
-            if (lane == 0) {
-                ItemBest* o = a.sb + task;
-                o->dchi2 = b.dchi2;
-                o->depth = b.depth;
-                o->start = (int32_t)b.start;
-                o->d = (int32_t)it.d;
-                o->evals = (int32_t)(m_hi - m_lo);
+            const uint32_t w = qb + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
+            if (w >= qe) break;
+            const int32_t fs = __builtin_amdgcn_readfirstlane(a.wfirst[w]);
+            RowItem ri[4];
+            int64_t g_lo[4], g_n[4], nw[4], dk[4];
+            int R = 0;
+            int64_t G = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int32_t idx = __builtin_amdgcn_readfirstlane(a.rowmap[fs + k]);
+                g_n[k] = 0;
+                g_lo[k] = 0;
+                nw[k] = 1;
+                dk[k] = 0;
+                ri[k].active = false;
+                ri[k].rp = ri[k].wp = ri[k].pf = ri[k].trow = nullptr;
+                ri[k].D = ri[k].s = ri[k].limit = ri[k].m_lo = ri[k].m_hi = 0;
+                ri[k].bconst = ri[k].s1 = 0.0;
+                if (idx < 0) continue;
+                int pl, j;
+                queue_item(a.bp, a.nd, idx, pl, j);
+                const double period = a.periods[pl];
+                const int64_t d = points_in(a.n, period, a.durations[j]);
+                const int64_t st = t0_stride(d, a.prm.dt0);
+                int Rk, rows;
+                int64_t groups;
+                item_rows(a, d, st, Rk, nw[k], groups, rows);
+                if (k == 0) R = Rk;                  // every row of a wave task has the same R
+                const int64_t t = (fs + k) - __builtin_amdgcn_readfirstlane(a.toff[idx]);
+                g_lo[k] = groups * t / rows;
+                g_n[k] = groups * (t + 1) / rows - g_lo[k];
+                G = max(G, g_n[k]);
+                dk[k] = d;
+                ri[k].rp = (const T*)a.rpad + (size_t)pl * a.pstride;
+                ri[k].wp = VARW ? (const void*)((const T*)a.wpad + (size_t)pl * a.pstride) : nullptr;
+                ri[k].pf = MEAN ? (const void*)((const char*)a.pfx + (size_t)pl * (a.pstride + 1) * pfs) : nullptr;
+                ri[k].trow = (const T*)a.table + trow_off(d);
+                ri[k].D = d;
+                ri[k].s = st;
+                ri[k].limit = a.n + d;
+                ri[k].bconst = VARW ? 0.0 : a.bsum[d];
+                ri[k].s1 = MEAN ? a.s1sum[d] : 0.0;
+            }
+            // An empty slot (only past the first row of a wave task, whose
+            // slot 0 always holds a row) takes row 0's curve, template and
+            // sizes, so every address its lanes form stays valid; it has no
+            // windows and its results are not written.
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                if (ri[k].rp == nullptr) {
+                    ri[k].rp = ri[0].rp;
+                    ri[k].wp = ri[0].wp;
+                    ri[k].pf = ri[0].pf;
+                    ri[k].trow = ri[0].trow;
+                    ri[k].D = ri[0].D;
+                    ri[k].s = ri[0].s;
+                    ri[k].limit = ri[0].limit;
+                    ri[k].bconst = ri[0].bconst;
+                    ri[k].s1 = ri[0].s1;
+                }
+            Best best{-INFINITY, 0.0, -1};
+            int64_t evals = 0;
+            for (int64_t g = 0; g < G; ++g) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    ri[k].active = g < g_n[k];
+                    ri[k].m_lo = min(nw[k], (g_lo[k] + g) * kRowLanes * R);
+                    ri[k].m_hi = min(nw[k], ri[k].m_lo + (int64_t)kRowLanes * R);
+                }
+                strided_rows_r<T, VARW, MEAN>(R, ri, best, evals, stage, stage_w);
+            }
+            best = row_best(best);
+            for (int off = 8; off > 0; off >>= 1) evals += __shfl_xor(evals, off);
+            const int32_t my_idx = pick4(row, a.rowmap[fs], a.rowmap[fs + 1], a.rowmap[fs + 2], a.rowmap[fs + 3]);
+            if ((lane & 15) == 0 && my_idx >= 0) {
+                ItemBest* o = a.sb + fs + row;
+                o->dchi2 = best.dchi2;
+                o->depth = best.depth;
+                o->start = (int32_t)best.start;
+                o->d = (int32_t)pick4(row, dk[0], dk[1], dk[2], dk[3]);
+                o->evals = (int32_t)evals;
                 o->ntiles = 0;
             }
         }
@@ -1596,7 +2038,8 @@ struct ReduceArgs {
     int32_t nd;
     const ItemBest* items;
     int32_t ntiles;
-    const int32_t* toff;     // strided items: task slots
+    const int32_t* toff;     // strided items: first row slot
+    const int32_t* tcnt;     // ... and row slots
     const ItemBest* sb;
     const uint64_t* keys_a;
     const uint64_t* misc;
@@ -1624,7 +2067,7 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
             if (t0_stride(points_in(a.n, period, a.durations[j]), a.prm.dt0) >= 2) {
                 const int64_t idx = queue_index(a.bp, a.nd, pl, j);
                 slots = a.sb + a.toff[idx];
-                nt = a.toff[idx + 1] - a.toff[idx];
+                nt = a.tcnt[idx];
             }
             for (int t = 0; t < nt; ++t) {
                 const ItemBest b = slots[t];
@@ -2281,9 +2724,17 @@ struct Plan {
     int32_t bp, ntiles;
     bool varw, mean, f32;
     size_t esize, psize;     // bytes per padded-curve element and per prefix element
-    size_t off_a, off_b, off_r, off_w, off_pf, off_items, off_toff, off_tmap, off_sb, off_queue, off_ulist, off_cnt,
-        off_ucnt, per_batch;
+    size_t off_a, off_b, off_r, off_w, off_pf, off_items, off_toff, off_tcnt, off_rowmap, off_wfirst, off_sb,
+        off_cell_s, off_cell_w, off_queue, off_ulist, off_ucnt, per_batch;
 };
+
+// Cells of the row planner for bp periods and nd durations (the device's
+// cell_count): the periods of each XCD's list in blocks of kCellItems.
+static int64_t host_cells(int64_t bp, int64_t nd) {
+    int64_t c = 0;
+    for (int x = 0; x < kXcds; ++x) c += (((bp - x + kXcds - 1) / kXcds) + kCellItems - 1) / kCellItems * nd;
+    return c;
+}
 
 Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm, bool varw, size_t budget) {
     Plan p{};
@@ -2301,7 +2752,7 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     size_t per = 2 * sizeof(uint64_t) * (size_t)n + p.esize * (size_t)p.pstride +
                  (varw ? p.esize * (size_t)p.pstride : 0) + (p.mean ? p.psize * (size_t)(p.pstride + 1) : 0) +
                  sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles +
-                 (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kTaskMax + 3 * sizeof(int32_t) * (size_t)nd +
+                 (sizeof(ItemBest) + 2 * sizeof(int32_t)) * (size_t)nd * kRowMax + 4 * sizeof(int32_t) * (size_t)nd +
                  1024;
     // Periods per launch: as many as the scratch budget holds, at most
     // 32768.  Fewer, larger launches leave fewer drained tails: on the
@@ -2324,17 +2775,28 @@ Plan make_plan(int64_t n, int32_t n_periods, int32_t nd, const gtls_params& prm,
     if (p.mean) o = align256(o + p.psize * (size_t)(p.pstride + 1) * bp);
     p.off_items = o;
     o = align256(o + sizeof(ItemBest) * (size_t)nd * (size_t)p.ntiles * bp);
+    // Row slots: at most kRowMax per strided item, plus the padding of each
+    // cell's subgroups to whole wave tasks (at most 3 per subgroup, at most
+    // kCellItems subgroups per cell).
+    const int64_t cells = host_cells(bp, nd);
+    const size_t slots = (size_t)nd * kRowMax * bp + (size_t)3 * kCellItems * cells;
     p.off_toff = o;
-    o = align256(o + sizeof(int32_t) * ((size_t)nd * bp + 1));
-    p.off_tmap = o;
-    o = align256(o + sizeof(int32_t) * (size_t)nd * kTaskMax * bp);
+    o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
+    p.off_tcnt = o;
+    o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
+    p.off_rowmap = o;
+    o = align256(o + sizeof(int32_t) * slots);
+    p.off_wfirst = o;
+    o = align256(o + sizeof(int32_t) * (slots / 4 + 1));
     p.off_sb = o;
-    o = align256(o + sizeof(ItemBest) * (size_t)nd * kTaskMax * bp);
+    o = align256(o + sizeof(ItemBest) * slots);
+    p.off_cell_s = o;
+    o = align256(o + sizeof(int32_t) * (size_t)(cells + 1));
+    p.off_cell_w = o;
+    o = align256(o + sizeof(int32_t) * (size_t)(cells + 1));
     p.off_queue = o;
     o = align256(o + (2 * kXcds + 2) * sizeof(uint32_t));
     p.off_ulist = o;
-    o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
-    p.off_cnt = o;
     o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
     p.off_ucnt = o;
     o = align256(o + sizeof(int32_t) * (size_t)nd * bp);
@@ -2349,9 +2811,11 @@ void launch_slides(gtls_ctx* ctx, const SlideArgs& la, int64_t units, bool strid
     {
         StageTimer tm(ctx, kStageSlide);
         const unsigned pgrid = (unsigned)(((int64_t)la.bp * la.nd + 255) / 256);
+        const unsigned cgrid = (unsigned)((host_cells(la.bp, la.nd) + 255) / 256);
         k_plan_count<<<pgrid, 256, 0, s>>>(la);
+        k_rplan_count<<<cgrid, 256, 0, s>>>(la);
         k_plan_scan<<<1, kPlanThreads, 0, s>>>(la);
-        if (strided) k_plan_fill<<<pgrid, 256, 0, s>>>(la);
+        k_rplan_fill<<<cgrid, 256, 0, s>>>(la);
         // every-offset work units (list entries x window tiles) by a grid of
         // at most as many workgroups as are resident at once
         int per_cu = 0;
@@ -2366,11 +2830,11 @@ void launch_slides(gtls_ctx* ctx, const SlideArgs& la, int64_t units, bool strid
         StageTimer tm(ctx, kStageStrided);
         // num_cus: compute units of the context's device, set at creation
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slide_strided<T, VARW, MEAN>, kSlideThreads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_slide_rows<T, VARW, MEAN>, kSlideThreads, 0) !=
                 hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        k_slide_strided<T, VARW, MEAN><<<(unsigned)(per_cu * num_cus), kSlideThreads, 0, s>>>(la);
+        k_slide_rows<T, VARW, MEAN><<<(unsigned)(per_cu * num_cus), kSlideThreads, 0, s>>>(la);
     }
 }
 
@@ -2474,11 +2938,14 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
     void* pfx = pl.mean ? (void*)(bb + pl.off_pf) : nullptr;
     ItemBest* items = (ItemBest*)(bb + pl.off_items);
     int32_t* toff = (int32_t*)(bb + pl.off_toff);
-    int32_t* tmap = (int32_t*)(bb + pl.off_tmap);
+    int32_t* tcnt = (int32_t*)(bb + pl.off_tcnt);
+    int32_t* rowmap = (int32_t*)(bb + pl.off_rowmap);
+    int32_t* wfirst = (int32_t*)(bb + pl.off_wfirst);
+    int32_t* cell_s = (int32_t*)(bb + pl.off_cell_s);
+    int32_t* cell_w = (int32_t*)(bb + pl.off_cell_w);
     ItemBest* sb = (ItemBest*)(bb + pl.off_sb);
     uint32_t* queue = (uint32_t*)(bb + pl.off_queue);
     int32_t* ulist = (int32_t*)(bb + pl.off_ulist);
-    int32_t* cnt = (int32_t*)(bb + pl.off_cnt);
     int32_t* ucnt = (int32_t*)(bb + pl.off_ucnt);
     const bool strided = a.prm.dt0 > 0.0;
 
@@ -2491,12 +2958,12 @@ hipError_t run_search(gtls_ctx* ctx, const SearchArgs& a) {
             k_fold_sort<<<bp, kSortThreads, 0, s>>>(sa);
         }
         SlideArgs la{a.periods + p0, a.durations, a.n_durations, bp, n, a.prm, rpad, wpad, pfx, pl.pstride,
-                     misc, table, bsum, s1sum, items, pl.ntiles, toff, tmap, sb, queue, pl.f32 ? 4 : 8,
-                     pl.f32 ? 0 : 1, ulist, cnt, ucnt};
+                     misc, table, bsum, s1sum, items, pl.ntiles, toff, tcnt, rowmap, wfirst, cell_s, cell_w, sb,
+                     queue, pl.f32 ? 4 : 8, pl.f32 ? 0 : 1, ulist, ucnt};
         const int64_t units = (int64_t)bp * a.n_durations * pl.ntiles;
         if (pl.f32) launch_slides<float>(ctx, la, units, strided, varw, pl.mean, ctx->num_cus, s);
         else launch_slides<double>(ctx, la, units, strided, varw, pl.mean, ctx->num_cus, s);
-        ReduceArgs ra{a.t, n, a.periods + p0, a.durations, a.prm, bp, a.n_durations, items, pl.ntiles, toff, sb,
+        ReduceArgs ra{a.t, n, a.periods + p0, a.durations, a.prm, bp, a.n_durations, items, pl.ntiles, toff, tcnt, sb,
                       keys_a, misc, misc,
                       a.chi2 + p0, a.best_dur + p0, a.best_start + p0, a.depth + p0, a.t0 + p0};
         {
