@@ -158,6 +158,39 @@ def survey_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def cnn_bench(args):
+    """Training throughput of the period-proposal network: Adam steps of batch
+    256 on seeded 4096-bin views (the BF16 MFMA forward and backward kernels,
+    the head, the loss and the update), then top-k inference."""
+    from paper_2607_00348_amd import gtls, synth
+    batch = 256
+    g = np.random.Generator(np.random.PCG64(23))
+    views = g.normal(0.0, 1.0, (batch, gtls.CNN_VIEW)).astype(np.float32)
+    labels = g.integers(0, gtls.CNN_BINS, batch).astype(np.int32)
+    ctx = gtls.Context(0)
+    net = gtls.Cnn(ctx, synth.cnn_init(0).astype(np.float32))
+    for w in range(args.warmup):
+        gtls.gtls_cnn_train_step(net, views, labels, lr=1e-3)
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gtls.gtls_cnn_train_step(net, views, labels, lr=1e-3)
+    el = (time.perf_counter() - t0) / args.steps
+    t1 = time.perf_counter()
+    gtls.gtls_cnn_topk(net, views, 32)
+    inf = time.perf_counter() - t1
+    # forward + backward flops of the convolutions: 2 * B * L * 32 * (C_in * 7) per layer, x3 with backward
+    conv_flops = sum(2.0 * batch * gtls.CNN_VIEW * 32 * (cin * 7) for cin in (1, 32, 32, 32, 32))
+    line = {"metric": "CNN training samples/s", "value": batch / el, "unit": "samples/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "cnn_train", "batch": batch, "view": gtls.CNN_VIEW, "bins": gtls.CNN_BINS},
+            "inference_ms_per_batch": inf * 1e3, "conv_tflops_fwd_bwd": 3.0 * conv_flops / el / 1e12}
+    net.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def sort_bytes(n: int, periods, durs, prm) -> float:
     """Algorithmic HBM bytes of the fold + sort + pad stage for one search:
     per element-period 8 B of t, three radix passes over the packed 8-byte
@@ -234,7 +267,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="kepler_3000d",
-                    choices=["kepler_3000d", "kepler_90d", "tess_13sector", "survey"])
+                    choices=["kepler_3000d", "kepler_90d", "tess_13sector", "survey", "cnn_train"])
     ap.add_argument("--curves", type=int, default=32, help="survey sample size (--workload survey)")
     ap.add_argument("--route-min", type=int, default=0,
                     help="survey: curves of at least this many points go through the single-curve kernels "
@@ -257,6 +290,9 @@ def main():
 
     if args.workload == "survey":
         survey_bench(args)
+        return
+    if args.workload == "cnn_train":
+        cnn_bench(args)
         return
 
     import torch
@@ -322,7 +358,7 @@ def main():
         macs = strided_macs if stage == "slide_strided" else float(n_macs) - strided_macs
         flops = 2.0 * macs / launches                     # one multiply-add per template point per window
         achieved = flops / (per_launch_ms * 1e-3) / 1e12
-        kernel = "k_slide_strided" if stage == "slide_strided" else "k_slide_unit"
+        kernel = "k_slide_rows" if stage == "slide_strided" else "k_slide_unit"
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(kernel, args),
                 "kernel": kernel, "per_launch_ms": per_launch_ms, "flops_per_launch": flops}
