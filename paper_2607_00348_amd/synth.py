@@ -21,6 +21,8 @@ Workloads (Kepler long cadence = 29.4 min):
 * ``curve_random`` -- a generic curve with seeded length/noise/transit.
 * ``injection_curve`` -- a 4-year, 30-min, 110 ppm white-noise set, half of
   it with one injected transit of P < 14 d (injection-recovery tests).
+* ``proposal_curve`` -- 3000-day curves with the 3000-day curve's gaps and
+  noise, 70 % carrying a transit (learned period proposal).
 
 Flux is produced in FP64, rounded to FP32 (the instruments' precision), and
 returned as FP64 holding FP32 values.
@@ -283,6 +285,44 @@ def injection_curve(index: int, n_curves: int, seed: int = 7, days: float = 1461
         y = y - transit_deficit(t, **tr)
     y = y + sigma * g.standard_normal(n)
     return _curve(t, _to_fp32_flux(y), np.full(n, sigma), transit=tr, sigma=sigma, name=f"injection_{index}")
+
+
+def proposal_curve(index: int, seed: int = 3, pos_frac: float = 0.7) -> dict:
+    """Curve `index` of the learned-proposal set: the 3000-day curve's cadence
+    (29.4 min, 146,939 cadences from t = 0), gaps (uniform-start blocks of
+    U(1, 5) d removed until >= 10 % of the cadences are gone) and noise
+    (100 ppm white + AR(1) red noise of stationary sigma 30 ppm, tau = 0.5 d,
+    dy = 104.4 ppm); a seeded fraction pos_frac of the curves carries one
+    transit with the survey's parameter distribution and P <= 500 d: P
+    log-uniform in [1, 500] d, p ~ U(0.01, 0.1), u1 ~ U(0.2, 0.6),
+    u2 ~ U(0.1, 0.4), b = 0, T14 of a circular orbit around a Sun-like star,
+    T0 ~ U(0, P)."""
+    from scipy.signal import lfilter
+    g = rng(seed * 1_000_003 + index + 1)
+    n_full = int(round(3000.0 / KEPLER_CADENCE_DAYS))
+    t = np.arange(n_full, dtype=np.float64) * KEPLER_CADENCE_DAYS
+    white, red, tau = 100e-6, 30e-6, 0.5
+    phi = math.exp(-KEPLER_CADENCE_DAYS / tau)
+    e = g.standard_normal(n_full) * (red * math.sqrt(1.0 - phi * phi))
+    e[0] = red * g.standard_normal()
+    ar = lfilter([1.0], [1.0, -phi], e)                           # ar[k] = phi ar[k-1] + e[k]
+    y = 1.0 + white * g.standard_normal(n_full) + ar
+    tr = None
+    if g.uniform() < pos_frac:
+        period = float(math.exp(g.uniform(math.log(1.0), math.log(500.0))))
+        p = float(g.uniform(0.01, 0.1))
+        u1, u2 = float(g.uniform(0.2, 0.6)), float(g.uniform(0.1, 0.4))
+        depth = p * p / (1.0 - u1 / 3.0 - u2 / 6.0)
+        tr = dict(period=period, t0=float(g.uniform(0.0, period)), t14=grazing_t14(period, 0.0, p), depth=depth,
+                  u1=u1, u2=u2, b=0.0)
+        y = y - transit_deficit(t, **tr)
+    keep = np.ones(n_full, dtype=bool)
+    while keep.sum() > 0.9 * n_full:
+        start = g.uniform(0.0, 3000.0)
+        keep &= ~((t >= start) & (t < start + g.uniform(1.0, 5.0)))
+    sig = math.sqrt(white ** 2 + red ** 2)
+    return _curve(t[keep], _to_fp32_flux(y[keep]), np.full(int(keep.sum()), sig), transit=tr, sigma=sig,
+                  name=f"proposal_{index}")
 
 
 def cnn_init(seed: int = 0) -> np.ndarray:
