@@ -239,14 +239,19 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     }
 }
 
-// dW[co][k][ci] partials: one wave per (sample, 256-position chunk, tap k),
-// K = 256 positions = 16 MFMA steps; operands staged through LDS.
+// dW[co][k][ci] partials: one wave per (sample, tap k) walks the sample's
+// 4096 positions in 256-position chunks (K = 256 positions = 16 MFMA steps
+// per chunk, operands staged through LDS), accumulating every chunk into the
+// same MFMA accumulators; the tap-0 wave also sums dz per channel (the bias
+// gradient's partial).  The partials are then reduced over the samples in a
+// fixed order, so gradients are deterministic.
 struct WGradArgs {
     const __bf16* dz;        // [B][L][32]
     const __bf16* in;        // [B][L][cin]
     int cin;
     int B;
-    float* partial;          // [B * L/256][32][KW][cin]
+    float* partial;          // [B][32][KW][cin]
+    float* bpartial;         // [B][32]
 };
 
 constexpr int kWgChunk = 256;
@@ -255,67 +260,64 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(WGradArgs a) {
     __shared__ __bf16 dzs[kWgChunk][C + 2];
     __shared__ __bf16 ins[kWgChunk + KW - 1][C + 2];
     const int lane = threadIdx.x;
-    const int chunks = L / kWgChunk;
     const int k = blockIdx.y;
-    const int bc = blockIdx.x;                      // sample * chunks + chunk
-    const int b = bc / chunks;
-    const int p0 = (bc - b * chunks) * kWgChunk;
-    for (int e = lane; e < kWgChunk * C; e += 64) {
-        const int pp = e / C, cc = e - pp * C;
-        dzs[pp][cc] = a.dz[((size_t)b * L + p0 + pp) * C + cc];
-    }
-    for (int e = lane; e < (kWgChunk + KW - 1) * a.cin; e += 64) {
-        const int pp = e / a.cin, cc = e - pp * a.cin;
-        const int pos = p0 + pp - 3;
-        ins[pp][cc] = (pos >= 0 && pos < L) ? a.in[((size_t)b * L + pos) * a.cin + cc] : (__bf16)0.0f;
-    }
-    __syncthreads();
+    const int b = blockIdx.x;
     const int row = lane & 31, half = lane >> 5;
     floatx16 acc;
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    for (int s = 0; s < kWgChunk / 16; ++s) {
-        bf16x8 av, bv;
-        for (int q = 0; q < 8; ++q) {
-            const int pp = 16 * s + 8 * half + q;
-            av[q] = dzs[pp][row];                                           // A[co][pos]
-            bv[q] = (row < a.cin) ? ins[pp + k][row] : (__bf16)0.0f;        // B[pos][ci]
+    float bsum = 0.0f;
+    for (int p0 = 0; p0 < L; p0 += kWgChunk) {
+        __syncthreads();
+        for (int e = lane; e < kWgChunk * C; e += 64) {
+            const int pp = e / C, cc = e - pp * C;
+            dzs[pp][cc] = a.dz[((size_t)b * L + p0 + pp) * C + cc];
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        for (int e = lane; e < (kWgChunk + KW - 1) * a.cin; e += 64) {
+            const int pp = e / a.cin, cc = e - pp * a.cin;
+            const int pos = p0 + pp - 3;
+            ins[pp][cc] = (pos >= 0 && pos < L) ? a.in[((size_t)b * L + pos) * a.cin + cc] : (__bf16)0.0f;
+        }
+        __syncthreads();
+        for (int s = 0; s < kWgChunk / 16; ++s) {
+            bf16x8 av, bv;
+            for (int q = 0; q < 8; ++q) {
+                const int pp = 16 * s + 8 * half + q;
+                av[q] = dzs[pp][row];                                           // A[co][pos]
+                bv[q] = (row < a.cin) ? ins[pp + k][row] : (__bf16)0.0f;        // B[pos][ci]
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+        if (k == 0 && lane < C)
+            for (int pp = 0; pp < kWgChunk; ++pp) bsum += (float)dzs[pp][lane];
     }
+    if (k == 0 && lane < C) a.bpartial[(size_t)b * C + lane] = bsum;
     const int col = lane & 31;
     if (col >= a.cin) return;
-    float* out = a.partial + (size_t)bc * C * KW * a.cin;
+    float* out = a.partial + (size_t)b * C * KW * a.cin;
     for (int r = 0; r < 16; ++r) {
         const int co = 8 * (r >> 2) + 4 * half + (r & 3);
         out[((size_t)co * KW + k) * a.cin + col] = acc[r];
     }
 }
 
-// Sum of the partials in chunk order, written in the flat (co, ci, k) order.
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int nparts, int cin,
-                                                      float* __restrict__ grad_w) {
-    const int i = blockIdx.x * 256 + threadIdx.x;          // over (co, k, ci)
+// Sum of the per-sample partials in sample order, written in the flat
+// (co, ci, k) order, and the bias gradient likewise.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial,
+                                                      const float* __restrict__ bpartial, int nparts, int cin,
+                                                      float* __restrict__ grad_w, float* __restrict__ grad_b) {
+    const int i = blockIdx.x * 256 + threadIdx.x;          // over (co, k, ci), then the 32 biases
     const int n = C * KW * cin;
-    if (i >= n) return;
-    float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * n + i];
-    const int co = i / (KW * cin), rem = i - co * KW * cin, k = rem / cin, ci = rem - k * cin;
-    grad_w[((size_t)co * cin + ci) * KW + k] = s;
-}
-
-// db[co] = sum over samples and positions of dz.
-__global__ __launch_bounds__(256) void k_bgrad(const __bf16* __restrict__ dz, int B, float* __restrict__ grad_b) {
-    __shared__ float red[256];
-    const int co = blockIdx.x;
-    float s = 0.0f;
-    for (int64_t i = threadIdx.x; i < (int64_t)B * L; i += 256) s += (float)dz[i * C + co];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    if (i < n) {
+        float s = 0.0f;
+        for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * n + i];
+        const int co = i / (KW * cin), rem = i - co * KW * cin, k = rem / cin, ci = rem - k * cin;
+        grad_w[((size_t)co * cin + ci) * KW + k] = s;
+    } else if (i < n + C) {
+        const int co = i - n;
+        float s = 0.0f;
+        for (int p = 0; p < nparts; ++p) s += bpartial[(size_t)p * C + co];
+        grad_b[co] = s;
     }
-    if (threadIdx.x == 0) grad_b[co] = red[0];
 }
 
 // ------------------------------------------------------------------------
@@ -529,7 +531,7 @@ hipError_t cnn_reserve(gtls_cnn* net, int B) {
     if ((e = hipMalloc(&net->dlogits, 4 * (size_t)B * NB)) != hipSuccess) return e;
     if ((e = hipMalloc(&net->losses, 4 * (size_t)B)) != hipSuccess) return e;
     if ((e = hipMalloc(&net->labels, 4 * (size_t)B)) != hipSuccess) return e;
-    if ((e = hipMalloc(&net->partial, 4 * (size_t)B * (L / kWgChunk) * C * KW * C)) != hipSuccess) return e;
+    if ((e = hipMalloc(&net->partial, 4 * (size_t)B * (C * KW * C + C))) != hipSuccess) return e;
     if ((e = hipMalloc(&net->views, 4 * (size_t)B * L)) != hipSuccess) return e;
     if ((e = hipMalloc(&net->bins, 4 * (size_t)B * NB)) != hipSuccess) return e;
     net->cap = B;
@@ -566,11 +568,12 @@ void cnn_backward(gtls_cnn* net, int B) {
     for (int l = NL - 1; l >= 0; --l) {
         const int cin = cin_of(l);
         const __bf16* in = l == 0 ? net->x : net->h[l - 1];
-        WGradArgs wa{dz, in, cin, B, net->partial};
-        k_conv_wgrad<<<dim3((unsigned)(B * (L / kWgChunk)), KW), 64, 0, s>>>(wa);
-        k_wgrad_reduce<<<(unsigned)((C * KW * cin + 255) / 256), 256, 0, s>>>(net->partial, B * (L / kWgChunk), cin,
-                                                                              net->grads + w_off(l));
-        k_bgrad<<<C, 256, 0, s>>>(dz, B, net->grads + b_off(l));
+        float* bpart = net->partial + (size_t)B * C * KW * C;
+        WGradArgs wa{dz, in, cin, B, net->partial, bpart};
+        k_conv_wgrad<<<dim3((unsigned)B, KW), 64, 0, s>>>(wa);
+        k_wgrad_reduce<<<(unsigned)((C * KW * cin + C + 255) / 256), 256, 0, s>>>(net->partial, bpart, B, cin,
+                                                                                 net->grads + w_off(l),
+                                                                                 net->grads + b_off(l));
         if (l > 0) {
             // dz_{l-1} = (W_l^T * dz_l) * gelu'(z_{l-1}): the forward kernel with flipped weights
             ConvArgs a{dz, C, net->wb + woffs[l], nullptr, B, nullptr, dzn, net->z[l - 1], 0};
