@@ -2,14 +2,18 @@
 //
 // Per trial period P (Sect. 2.3 of the GTLS paper):
 //   k_fold_sort   one 1024-thread workgroup per period: phase fold on raw
-//                 times (Sect. 2.3.1), 24-bit fixed-point phase keys, a
-//                 3-pass stable LSD radix sort (8-bit digits) with wave-ballot
-//                 ranking, a tie-fix of equal keys by full FP64 phase then
-//                 input index, then the cyclic padding (Sect. 2.3.2): the
-//                 folded residuals (and weights) gathered in phase order for
-//                 n + D_max positions, and (moving-average depth only) exact
-//                 integer prefix sums of 1 - y over the padded curve
-//                 (Sect. 2.3.3).
+//                 times (Sect. 2.3.1) and the order of the points by (FP64
+//                 phase, index), in two phases over 32-bit fixed-point phase
+//                 keys: one counting pass over HBM by the top 8 key bits,
+//                 then LDS tiles of whole top-digit buckets ordered by the
+//                 next 8 bits and, within those bins, by rank; periods whose
+//                 phases bunch too tightly for the LDS tiles take a 3-pass
+//                 stable LSD radix sort over 24-bit keys (wave-ballot
+//                 ranking, equal keys fixed by FP64 phase then index).  Then
+//                 the cyclic padding (Sect. 2.3.2): the folded residuals (and
+//                 weights) gathered in phase order for n + D_max positions,
+//                 and (moving-average depth only) exact integer prefix sums
+//                 of 1 - y over the padded curve (Sect. 2.3.3).
 //   k_plan_*      per launch: the every-offset items and the wave tasks of
 //                 the items with a T0 step of two or more points.
 //   k_slide_unit  every T0 offset (Sect. 2.3.4, in-transit term): work units
@@ -276,6 +280,13 @@ __device__ __forceinline__ uint32_t phase_key(double ph) {
     return x >= kTwo24 ? kKeyMax : (uint32_t)x;
 }
 
+// 32-bit key floor(phi 2^32) of the two-phase sort, monotone in phi (equal
+// keys: phases within 2^-32 of each other).
+__device__ __forceinline__ uint32_t phase_key32(double ph) {
+    const double x = ph * 4294967296.0;
+    return x >= 4294967296.0 ? 0xffffffffu : (uint32_t)x;
+}
+
 // Zeros kept after every padded curve of the single-curve search: the
 // strided slide reads 16-byte pieces that start at most at the end of the
 // padded curve.
@@ -323,6 +334,84 @@ __device__ __forceinline__ void pad_store(const PadOut& po, int64_t n, int64_t p
     pad_put(po, n, pos, po.r[idx], po.wpad ? po.w[idx] : 0.0);
 }
 
+// Stable rank of each item's 8-bit digit (bits shift..shift+7) among the
+// items of this wave that precede it: items are in (item, lane) order, item
+// e of lane l at segment position e*64 + l, and the first `valid` positions
+// hold items.  wcnt is this wave's per-digit count, advanced by the wave's
+// items.
+template <int ITEMS>
+__device__ __forceinline__ void wave_rank(const uint64_t (&item)[ITEMS], int valid, int shift, uint32_t* wcnt,
+                                          uint32_t (&dig)[ITEMS], uint32_t (&rnk)[ITEMS]) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int e = 0; e < ITEMS; ++e) {
+        const bool active = e * 64 + lane < valid;
+        const uint32_t d = active ? (uint32_t)(item[e] >> shift) & 255u : 0u;
+        // lanes whose digit differs in some bit: ballot(bit) XOR this
+        // lane's bit spread over 32 bits, OR-ed over the 8 bits
+        uint32_t dlo = 0u, dhi = 0u;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t m = __ballot(sb != 0u);
+            dlo |= (uint32_t)m ^ sb;
+            dhi |= (uint32_t)(m >> 32) ^ sb;
+        }
+        const uint64_t peers = __ballot(active) & ~(((uint64_t)dhi << 32) | dlo);
+        const uint32_t before = __popcll(peers & lt_mask);
+        uint32_t cnt = 0;
+        if (active) cnt = wcnt[d];
+        __builtin_amdgcn_wave_barrier();
+        if (active && before == 0) wcnt[d] = cnt + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        rnk[e] = cnt + before;
+        dig[e] = d;
+    }
+}
+
+// Items of a wave segment that starts at seg0 when lim items exist.
+template <int ITEMS>
+__device__ __forceinline__ int seg_valid(int64_t seg0, int64_t lim) {
+    const int64_t v = lim - seg0;
+    return v <= 0 ? 0 : (v >= 64 * ITEMS ? 64 * ITEMS : (int)v);
+}
+
+// After every wave has ranked a tile (and a barrier): per digit, the waves'
+// exclusive offsets within the digit (wcnt), the tile's count (tcount) and
+// the digit's first slot in the tile's digit order (tstart).  Ends with a
+// barrier.
+template <int NT, int ITEMS>
+__device__ __forceinline__ void tile_offsets(SortShared<NT, ITEMS>& sh) {
+    constexpr int W = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    if (tid < 256) {
+        uint32_t run = 0;
+        for (int w2 = 0; w2 < W; ++w2) {
+            const uint32_t c = sh.wcnt[w2][tid];
+            sh.wcnt[w2][tid] = run;
+            run += c;
+        }
+        sh.tcount[tid] = run;
+        // inclusive scan of the counts over the 256 digits: per wave, then across waves
+        uint32_t v = run;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(v, off);
+            if (lane >= off) v += o;
+        }
+        if (lane == 63) sh.wtot[tid >> 6] = v;
+        sh.tstart[tid] = v - run;
+    }
+    __syncthreads();
+    if (tid >= 64 && tid < 256) {
+        uint32_t add = 0;
+        for (int w2 = 0; w2 < (tid >> 6); ++w2) add += sh.wtot[w2];
+        sh.tstart[tid] += add;
+    }
+    __syncthreads();
+}
+
 // Phase order of n points at `period`: A[k] = (phase key << 32 | index) of
 // the k-th point, and (Sect. 2.3.2) the padded residuals in that order.
 // Three stable 8-bit LSD passes over 24-bit keys, ranked with wave ballots:
@@ -361,7 +450,6 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
     }
     __syncthreads();
 
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const bool gather = po.rpad != nullptr;
     for (int pass = 0; pass < 3; ++pass) {
         const uint64_t* src = (pass == 2) ? B : A;
@@ -391,60 +479,12 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
             }
             const int64_t seg0 = tile0 + (int64_t)wave * 64 * ITEMS;
             uint32_t dig[ITEMS], rnk[ITEMS];
-#pragma unroll
-            for (int e = 0; e < ITEMS; ++e) {
-                const int64_t idx = seg0 + e * 64 + lane;
-                const bool active = idx < n;
-                const uint32_t d = active ? (uint32_t)(item[e] >> shift) & 255u : 0u;
-                // lanes whose digit differs in some bit: ballot(bit) XOR this
-                // lane's bit spread over 32 bits, OR-ed over the 8 bits
-                uint32_t dlo = 0u, dhi = 0u;
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-                    const uint64_t m = __ballot(sb != 0u);
-                    dlo |= (uint32_t)m ^ sb;
-                    dhi |= (uint32_t)(m >> 32) ^ sb;
-                }
-                const uint64_t peers = __ballot(active) & ~(((uint64_t)dhi << 32) | dlo);
-                const uint32_t before = __popcll(peers & lt_mask);
-                uint32_t cnt = 0;
-                if (active) cnt = sh.wcnt[wave][d];
-                __builtin_amdgcn_wave_barrier();
-                if (active && before == 0) sh.wcnt[wave][d] = cnt + (uint32_t)__popcll(peers);
-                __builtin_amdgcn_wave_barrier();
-                rnk[e] = cnt + before;
-                dig[e] = d;
-            }
+            wave_rank<ITEMS>(item, seg_valid<ITEMS>(seg0, n), shift, sh.wcnt[wave], dig, rnk);
             if constexpr (PREFETCH) {
                 if (tile0 + TILE < n) fetch(tile0 + TILE, nxt);
             }
             __syncthreads();
-            // per digit: the waves' exclusive offsets within the tile, and the tile's count
-            if (tid < 256) {
-                uint32_t run = 0;
-                for (int w2 = 0; w2 < W; ++w2) {
-                    const uint32_t c = sh.wcnt[w2][tid];
-                    sh.wcnt[w2][tid] = run;
-                    run += c;
-                }
-                sh.tcount[tid] = run;
-                // inclusive scan of the counts over the 256 digits: per wave, then across waves
-                uint32_t v = run;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t o = __shfl_up(v, off);
-                    if (lane >= off) v += o;
-                }
-                if (lane == 63) sh.wtot[tid >> 6] = v;
-                sh.tstart[tid] = v - run;
-            }
-            __syncthreads();
-            if (tid >= 64 && tid < 256) {
-                uint32_t add = 0;
-                for (int w2 = 0; w2 < (tid >> 6); ++w2) add += sh.wtot[w2];
-                sh.tstart[tid] += add;
-            }
-            __syncthreads();
+            tile_offsets(sh);
             // the tile in digit order (stable: waves, then items, then lanes, follow input order) ...
 #pragma unroll
             for (int e = 0; e < ITEMS; ++e) {
@@ -536,6 +576,317 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
         }
     }
     __syncthreads();
+}
+
+// The same order in two phases over 32-bit keys floor(phi 2^32), with
+// atomic (unstable) counting; the order is still unique, since each group of
+// equal 16-bit key prefixes is finally ranked by (key, FP64 phase, index).
+//   1. the top 8 key bits: a histogram of the buckets, then per tile of
+//      input points a rank of each point within its bucket (LDS atomics),
+//      the tile gathered in bucket order in LDS and written to the buckets'
+//      runs of A (t -> A);
+//   2. LDS tiles of whole buckets (at most NT * ITEMS points and
+//      kTileBuckets buckets): the same counting step over the next 8 key bits
+//      of each bucket (kTileBuckets * 256 bins); each word's place in its bin
+//      is the number of the bin's words that precede it in (key, phase,
+//      index) order; the tile is written back to A in place with its padded
+//      copies.
+// A then holds (32-bit key << 32 | index) in phase order; its indices are
+// those of the three-pass sort.  Returns false, leaving A and the padded
+// copies to be rewritten, when a bucket holds more than NT * ITEMS points or
+// a bin more than kBinCap (phases bunched within 2^-16 of a period); the
+// caller then runs fold_sort_core.
+constexpr int kTileBuckets = 32;
+constexpr int kBins = kTileBuckets * 256;
+constexpr uint32_t kBinCap = 64;
+
+template <int NT>
+struct SortTwoPhase {
+    uint32_t bins[kBins];        // per tile: counts, then first slots, of (bucket, next digit) bins
+    uint32_t wsum[NT / 64];
+    int32_t tiles[257];          // first bucket of each LDS tile, then 256
+    int32_t ntiles;
+    int32_t fallback;
+};
+
+template <int NT, int ITEMS>
+__device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, double period, uint64_t* A,
+                                   const PadOut& po, SortShared<NT, ITEMS>& sh, SortTwoPhase<NT>& sx) {
+    constexpr int TILE = NT * ITEMS;
+    constexpr int BPT = kBins / NT;      // bins per thread in the scan
+    static_assert(kBins % NT == 0 && ITEMS % 2 == 0 && TILE < 65536, "bins per thread, halves of a tile, slots");
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    uint32_t* const off = sh.hist[2];    // bucket d: first position in A
+    for (int k = tid; k < 256; k += NT) {
+        off[k] = 0;
+        sh.tcount[k] = 0;
+    }
+    if (tid == 0) sx.fallback = 0;
+    __syncthreads();
+    // ITEMS loads in flight per thread before the keys are counted
+    for (int64_t i0 = 0; i0 < n; i0 += (int64_t)NT * ITEMS) {
+        double tv[ITEMS];
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) {
+            const int64_t i = i0 + (int64_t)e * NT + tid;
+            tv[e] = i < n ? t[i] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e)
+            if (i0 + (int64_t)e * NT + tid < n) atomicAdd(&off[phase_key32(phase_of(tv[e], period)) >> 24], 1u);
+    }
+    __syncthreads();
+    // wave 0: exclusive offsets of 256 counts (four per lane) into dst, and
+    // whether any count exceeds cap
+    auto scan256 = [&](const uint32_t* cnt, uint32_t* dst, uint32_t cap) {
+        uint32_t c[4], sum = 0, mx = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = cnt[4 * lane + q];
+            sum += c[q];
+            mx = max(mx, c[q]);
+        }
+        uint32_t v = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(v, o);
+            if (lane >= o) v += u;
+        }
+        uint32_t run = v - sum;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dst[4 * lane + q] = run;
+            run += c[q];
+        }
+        return __ballot(mx > cap) != 0ull;
+    };
+    if (wave == 0) {
+        const bool big = scan256(off, off, (uint32_t)TILE);
+        if (lane == 0 && big) sx.fallback = 1;
+    }
+    __syncthreads();
+    if (sx.fallback) return false;
+    if (wave == 0) {
+        // LDS tiles: greedy runs of whole buckets, at most TILE points and
+        // kTileBuckets buckets.  Bucket d joins the tile opened at bucket b
+        // while off[d + 1] <= off[b] + TILE and d - b < kTileBuckets; both
+        // hold for a prefix of the lanes, whose count is the step.
+        auto end_of = [&](int d) -> uint32_t { return d + 1 < 256 ? off[d + 1] : (uint32_t)n; };
+        int b = 0, nt = 0;
+        while (b < 256) {
+            if (lane == 0) sx.tiles[nt] = b;
+            ++nt;
+            const uint32_t lim = off[b] + (uint32_t)TILE;
+            const int b0 = b;
+            for (;;) {
+                const int d = b + lane;
+                const uint64_t acc = __ballot(d < 256 && d - b0 < kTileBuckets && end_of(d) <= lim);
+                const int cnt = __popcll(acc);
+                b += cnt;
+                if (cnt < 64) break;
+            }
+        }
+        if (lane == 0) {
+            sx.tiles[nt] = 256;
+            sx.ntiles = nt;
+        }
+    }
+    for (int k = tid; k < 256; k += NT) sh.dbase[k] = off[k];
+    __syncthreads();
+
+    // 1. the top-digit pass, t -> A; the next tile's times are loaded while
+    // the current tile is ranked and written
+    double tv[ITEMS];
+    auto fetch = [&](int64_t tile0) {
+        const int64_t seg0 = tile0 + (int64_t)wave * 64 * ITEMS;
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) {
+            const int64_t idx = seg0 + e * 64 + lane;
+            tv[e] = idx < n ? t[idx] : 0.0;
+        }
+    };
+    uint64_t item[ITEMS];
+    uint32_t rk[ITEMS];
+    fetch(0);
+    for (int64_t tile0 = 0; tile0 < n; tile0 += TILE) {
+        {
+            const int64_t seg0 = tile0 + (int64_t)wave * 64 * ITEMS;
+#pragma unroll
+            for (int e = 0; e < ITEMS; ++e)
+                item[e] = ((uint64_t)phase_key32(phase_of(tv[e], period)) << 32) | (uint32_t)(seg0 + e * 64 + lane);
+        }
+        const int valid = seg_valid<ITEMS>(tile0 + (int64_t)wave * 64 * ITEMS, n);
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e)
+            if (e * 64 + lane < valid) rk[e] = atomicAdd(&sh.tcount[(uint32_t)(item[e] >> 56)], 1u);
+        if (tile0 + TILE < n) fetch(tile0 + TILE);
+        __syncthreads();
+        if (wave == 0) (void)scan256(sh.tcount, sh.tstart, 0xffffffffu);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e)
+            if (e * 64 + lane < valid) sh.buf[sh.tstart[(uint32_t)(item[e] >> 56)] + rk[e]] = item[e];
+        __syncthreads();
+        const int tn = (int)min((int64_t)TILE, n - tile0);
+        for (int i = tid; i < tn; i += NT) {
+            const uint64_t it = sh.buf[i];
+            const uint32_t d = (uint32_t)(it >> 56);
+            const uint32_t pos = sh.dbase[d] + (uint32_t)i - sh.tstart[d];
+            if (pos < (uint32_t)n) A[pos] = it;
+        }
+        __syncthreads();
+        if (tid < 256) {
+            sh.dbase[tid] += sh.tcount[tid];
+            sh.tcount[tid] = 0;
+        }
+        __syncthreads();
+    }
+
+    // 2. LDS tiles of whole buckets (no prefetch of the next tile: its
+    // registers would push the kernel into spills)
+    const bool gather = po.rpad != nullptr;
+    const int ntiles = sx.ntiles;
+    const int wseg = wave * 64 * ITEMS + lane;           // this lane's first position in a tile
+    auto tile_base = [&](int j) -> uint32_t { return off[sx.tiles[j]]; };
+    auto tile_end = [&](int j) -> uint32_t { return sx.tiles[j + 1] < 256 ? off[sx.tiles[j + 1]] : (uint32_t)n; };
+    auto load = [&](int j, uint64_t (&it)[ITEMS]) {
+        const uint32_t base = tile_base(j);
+        const int m = (int)(tile_end(j) - base);
+        const uint64_t* src = A + base + wseg;
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) it[e] = wseg + e * 64 < m ? src[e * 64] : 0ull;
+    };
+    // (key, FP64 phase, index) order of two words
+    auto word_less = [&](uint64_t a, uint64_t b) -> bool {
+        const uint32_t ka = (uint32_t)(a >> 32), kb = (uint32_t)(b >> 32);
+        return ka != kb ? ka < kb : key_less(a, b, t, period);
+    };
+    for (int j = 0; j < ntiles; ++j) {
+        load(j, item);
+        const uint32_t base = tile_base(j);
+        const int m = (int)(tile_end(j) - base);
+        const uint32_t bin0 = (uint32_t)sx.tiles[j] << 8;
+        const int nbins = (sx.tiles[j + 1] - sx.tiles[j]) * 256;
+        const int valid = seg_valid<ITEMS>(wave * 64 * ITEMS, m);
+        for (int k = tid; k < nbins; k += NT) sx.bins[k] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e)
+            if (e * 64 + lane < valid) rk[e] = atomicAdd(&sx.bins[(uint32_t)(item[e] >> 48) - bin0], 1u);
+        __syncthreads();
+        // exclusive scan of the nbins counts: BPT consecutive bins per thread
+        uint32_t c[BPT], sum = 0;
+        bool big = false;
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int k = tid * BPT + q;
+            c[q] = k < nbins ? sx.bins[k] : 0u;
+            sum += c[q];
+            big |= c[q] > kBinCap;
+        }
+        uint32_t v = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(v, o);
+            if (lane >= o) v += u;
+        }
+        if (lane == 63) sx.wsum[wave] = v;
+        if (big) sx.fallback = 1;
+        __syncthreads();
+        if (sx.fallback) return false;
+        uint32_t run = v - sum;
+        for (int w2 = 0; w2 < wave; ++w2) run += sx.wsum[w2];
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int k = tid * BPT + q;
+            if (k < nbins) sx.bins[k] = run;
+            run += c[q];
+        }
+        __syncthreads();
+        // each word into its bin's run, then its place within the run: the
+        // number of the run's words ordered before it (the runs are short;
+        // the ITEMS words of a thread step through their runs together)
+        uint32_t span[ITEMS];                 // the bin's first slot | its end << 16 (slots < 2^16)
+        int steps = 0;
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) {
+            span[e] = 0u;
+            if (e * 64 + lane < valid) {
+                const uint32_t b = (uint32_t)(item[e] >> 48) - bin0;
+                const uint32_t r0 = sx.bins[b];
+                const uint32_t r1 = (int)b + 1 < nbins ? sx.bins[b + 1] : (uint32_t)m;
+                span[e] = r0 | (r1 << 16);
+                sh.buf[r0 + rk[e]] = item[e];
+                steps = max(steps, (int)(r1 - r0));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e) rk[e] = 0u;
+        // keys first; a word that meets an equal key in its run (phases
+        // within 2^-32) is recounted with the full order
+        uint32_t ties = 0u;
+        for (int q = 0; q < steps; ++q) {
+#pragma unroll
+            for (int e = 0; e < ITEMS; ++e) {
+                const uint32_t x = (span[e] & 0xffffu) + (uint32_t)q;
+                if (x < (span[e] >> 16)) {
+                    const uint64_t o = sh.buf[x];
+                    const uint32_t ko = (uint32_t)(o >> 32), ki = (uint32_t)(item[e] >> 32);
+                    rk[e] += ko < ki ? 1u : 0u;
+                    if (ko == ki && o != item[e]) ties |= 1u << e;
+                }
+            }
+        }
+        if (ties) {
+#pragma unroll
+            for (int e = 0; e < ITEMS; ++e) {
+                if (ties & (1u << e)) {
+                    uint32_t r = 0u;
+                    for (uint32_t x = span[e] & 0xffffu; x < (span[e] >> 16); ++x)
+                        if (word_less(sh.buf[x], item[e])) ++r;
+                    rk[e] = r;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < ITEMS; ++e)
+            if (e * 64 + lane < valid) sh.buf[(span[e] & 0xffffu) + rk[e]] = item[e];
+        __syncthreads();
+        // the sorted tile to A and its padded copies, in two halves: every
+        // residual (and weight) of a half gathered before any is stored
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            constexpr int HI = ITEMS / 2;
+            uint64_t wd[HI];
+            double rv[HI], wv[HI];
+#pragma unroll
+            for (int e = 0; e < HI; ++e) {
+                const int i = (h * HI + e) * NT + tid;
+                wd[e] = i < m ? sh.buf[i] : 0ull;
+            }
+            if (gather) {
+#pragma unroll
+                for (int e = 0; e < HI; ++e) {
+                    const bool in = (h * HI + e) * NT + tid < m;
+                    const uint32_t idx = (uint32_t)wd[e];
+                    rv[e] = in ? po.r[idx] : 0.0;
+                    wv[e] = in && po.wpad ? po.w[idx] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < HI; ++e) {
+                const int i = (h * HI + e) * NT + tid;
+                if (i < m) {
+                    A[base + i] = wd[e];
+                    if (gather) pad_put(po, n, (int64_t)base + i, rv[e], wv[e]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    return true;
 }
 
 // Moving-average depth: prefix sums of 1 - y over the npad padded positions
@@ -643,6 +994,7 @@ struct SortArgs {
 // One workgroup per period of the batch.
 __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
     __shared__ SortShared<kSortThreads> sh;
+    __shared__ SortTwoPhase<kSortThreads> sx;
     const int pl = blockIdx.x;
     const double period = a.periods[pl];
     const int64_t n = a.n;
@@ -655,7 +1007,8 @@ __global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
     const size_t ps = a.f32 ? sizeof(float2) : sizeof(__int128);
     PadOut po{a.r, a.w, a.rpad ? (char*)a.rpad + (size_t)pl * a.pstride * es : nullptr,
               a.wpad ? (char*)a.wpad + (size_t)pl * a.pstride * es : nullptr, npad, a.f32 != 0};
-    fold_sort_core<kSortThreads, true>(a.t, n, period, A, B, po, sh);
+    if (!fold_sort_twophase<kSortThreads, kSortItems>(a.t, n, period, A, po, sh, sx))
+        fold_sort_core<kSortThreads, true>(a.t, n, period, A, B, po, sh);
     pad_prefix<kSortThreads>(A, n, npad, a.u, a.pfx ? (char*)a.pfx + (size_t)pl * (a.pstride + 1) * ps : nullptr,
                              a.f32 != 0, sh);
     if (po.rpad) {

@@ -74,6 +74,25 @@ def test_fold_sort_with_phase_ties(ctx, oracle):
         assert np.array_equal(got, oracle.fold_sort(t, p))
 
 
+def test_fold_sort_sizes_and_clustered_phases(ctx, oracle):
+    """Sizes around the 8192-word LDS tile, and phases bunched within 1/256 of
+    a period: a bucket of the top key digit then holds more points than one
+    LDS tile, and the sort takes its three-pass route."""
+    g = synth.rng(17)
+    for n in (1, 2, 63, 8192, 8193, 16389):
+        t = np.sort(g.uniform(0.0, 300.0, n))
+        for p in (0.37, 11.0, 290.0):
+            _say("fold_sort size", n, p)
+            got = gtls.tls_fold_sort(ctx, t, np.array([p]))[0]
+            assert np.array_equal(got, oracle.fold_sort(t, p)), (n, p)
+    n, cad = 40000, 0.02
+    t = np.arange(n) * cad
+    for p in (2 * cad * (1 + 1 / (256 * n)), 2 * cad, 5 * cad * (1 - 1 / (512 * n)), 0.7):
+        _say("fold_sort clustered", n, p)
+        got = gtls.tls_fold_sort(ctx, t, np.array([p]))[0]
+        assert np.array_equal(got, oracle.fold_sort(t, p)), p
+
+
 def test_sde_kernel_matches_oracle(ctx, oracle):
     for n, w in ((1, 1), (50, 91), (3000, 91), (100000, 91), (4000, 5)):
         chi2 = synth.random_chi2_series(n, n)
