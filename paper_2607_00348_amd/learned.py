@@ -95,8 +95,11 @@ def views_of(ctx, curves) -> np.ndarray:
                               np.concatenate([c["y"] for c in curves]))
 
 
-def train(ctx, views, labels, steps: int, batch: int = 64, lr: float = 1e-3, seed: int = 0, log=None):
-    net = gtls.Cnn(ctx, synth.cnn_init(seed).astype(np.float32))
+def train(ctx, views, labels, steps: int, batch: int = 64, lr: float = 1e-3, seed: int = 0, log=None, net=None):
+    """Adam steps on random batches (warm-up over 100 steps, cosine decay);
+    a new network from the seeded initialisation unless `net` is given."""
+    if net is None:
+        net = gtls.Cnn(ctx, synth.cnn_init(seed).astype(np.float32))
     g = synth.rng(seed + 1)
     losses = []
     for s in range(steps):
@@ -226,5 +229,225 @@ def main(argv=None):
             f.write(s + "\n")
 
 
+
+
+# --------------------------------------------------------------------------
+# The learned proposal on its configured workload: 3000-day curves with the
+# 3000-day curve's gaps and noise (synth.proposal_curve), the full Ofir grid
+# 0.5-1500 d (418,590 periods), 20 durations, T0 step 0.1, FP64.  Labels are
+# the full-grid best periods; the pruned search is compared with the plain
+# search and with two proposers that use no network: the prior ranking of the
+# training labels' bins, and the coarse first pass of the two-stage search
+# (Sect. 2.5: T0 step 0.5 over the grid, then the T0 step 0.1 on the periods
+# with the largest coarse SDE).
+
+C4_PMIN, C4_PMAX, C4_DT0 = 0.5, 1500.0, 0.1
+
+
+def c4_inputs():
+    span = (int(round(3000.0 / synth.KEPLER_CADENCE_DAYS)) - 1) * synth.KEPLER_CADENCE_DAYS
+    grid = gtls.gtls_period_grid_ofir(span, 3.0, pmin_days=C4_PMIN, pmax_days=C4_PMAX)
+    durs = gtls.gtls_duration_grid(C4_PMIN, C4_PMAX, 20)
+    tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    return grid, durs, tm
+
+
+def c4_bin(p) -> np.ndarray:
+    """Geometric bin over [0.5, 1500] d, as tls_search_pruned assigns it."""
+    b = np.floor(np.log(np.asarray(p) / C4_PMIN) / math.log(C4_PMAX / C4_PMIN) * N_BINS)
+    return np.clip(b, 0, N_BINS - 1).astype(np.int32)
+
+
+def _gen(i):
+    return synth.proposal_curve(int(i))
+
+
+def _curves(indices, workers=8):
+    from multiprocessing import get_context
+    with get_context("spawn").Pool(workers) as pool:
+        return pool.map(_gen, list(indices), chunksize=4)
+
+
+def _injected_views(ctx, i0: int, count: int, workers: int = 16, chunk: int = 256, log=print):
+    """Views and injected-period bins of the curves among [i0, i0 + count)
+    that carry a transit (no search: the label is the bin of the injected
+    period)."""
+    from multiprocessing import get_context
+    views, labels = [], []
+    with get_context("spawn").Pool(workers) as pool:
+        for c0 in range(i0, i0 + count, chunk):
+            cs = pool.map(_gen, list(range(c0, min(i0 + count, c0 + chunk))), chunksize=8)
+            cs = [c for c in cs if c["meta"]["transit"] is not None]
+            if cs:
+                views.append(views_of(ctx, cs))
+                labels.append(c4_bin([c["meta"]["transit"]["period"] for c in cs]))
+            if ((c0 - i0) // chunk) % 8 == 7:
+                log(f"pretraining views: {sum(len(v) for v in views)} from {c0 + chunk - i0} curves")
+    return np.concatenate(views), np.concatenate(labels)
+
+
+def c4_label(i0: int, i1: int, out: str, log=print):
+    """Full-grid searches of proposal curves [i0, i1): best period index and
+    SDE per curve, saved to `out` (npz) as they come."""
+    ctx = gtls.Context(0)
+    grid, durs, tm = c4_inputs()
+    prm = gtls.gtls_params_default(dt0=C4_DT0)
+    idx, best, sde = [], [], []
+    t0 = time.perf_counter()
+    for c0 in range(i0, i1, 32):
+        cs = _curves(range(c0, min(i1, c0 + 32)))
+        for k, c in enumerate(cs):
+            r = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], grid, durs, tm, prm)
+            idx.append(c0 + k)
+            best.append(r.best_period)
+            sde.append(r.sde_max)
+        np.savez(out, index=np.array(idx), best=np.array(best), sde=np.array(sde), n_periods=len(grid))
+        log(f"labelled {len(idx)} curves in {time.perf_counter() - t0:.0f} s")
+    ctx.close()
+
+
+def c4_eval(label_files, n_test: int, steps: int, batch: int = 64, lr: float = 1e-3, seed: int = 0,
+            ks=(32, 64, 128), accepts=(7.0, 10.0, 15.0), refines=(200, 2000, 20000), log=print,
+            pretrain: int = 0, pre_steps: int = 0, baselines: bool = True) -> dict:
+    """Train on the search labels of `label_files` (after pretraining, when
+    `pretrain` > 0, for `pre_steps` steps on the injected-period bins of that
+    many further curves, indices from 20,000,000), then score the pruned
+    search (and, with `baselines`, the prior-only ranking and the two-stage
+    coarse pass) on n_test held-out curves against the full grid."""
+    grid, durs, tm = c4_inputs()
+    gbin = c4_bin(grid)
+    idx, best = [], []
+    for f in label_files:
+        d = np.load(f)
+        assert int(d["n_periods"]) == len(grid)
+        idx.extend(d["index"].tolist())
+        best.extend(d["best"].tolist())
+    order = np.argsort(idx)
+    idx, best = np.array(idx)[order], np.array(best)[order]
+    labels = gbin[best]
+    ctx = gtls.Context(0)
+    t0 = time.perf_counter()
+    train_views = []
+    for c0 in range(0, len(idx), 64):
+        cs = _curves(idx[c0:c0 + 64])
+        train_views.append(views_of(ctx, cs))
+    v_tr = np.concatenate(train_views)
+    log(f"{len(idx)} training views in {time.perf_counter() - t0:.0f} s")
+    net, n_pre, t_pre = None, 0, 0.0
+    if pretrain > 0:
+        t0 = time.perf_counter()
+        v_pre, l_pre = _injected_views(ctx, 20_000_000, pretrain, log=log)
+        n_pre = len(v_pre)
+        net, _ = train(ctx, v_pre, l_pre, pre_steps, batch=batch, lr=lr, seed=seed, log=log)
+        t_pre = time.perf_counter() - t0
+        log(f"pretrained on {n_pre} injected-period views in {t_pre:.0f} s")
+    t0 = time.perf_counter()
+    net, losses = train(ctx, v_tr, labels, steps, batch=batch, lr=lr, seed=seed, log=log, net=net)
+    t_train = time.perf_counter() - t0
+    prior = np.argsort(-np.bincount(labels, minlength=N_BINS), kind="stable")
+    prm = gtls.gtls_params_default(dt0=C4_DT0)
+    coarse_prm = gtls.gtls_params_default(dt0=0.5)
+    rec = []
+    test = _curves(range(10_000_000, 10_000_000 + n_test))
+    for i, c in enumerate(test):
+        r = {}
+        t1 = time.perf_counter()
+        full = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], grid, durs, tm, prm)
+        r["t_full"] = time.perf_counter() - t1
+        r["best"] = int(full.best_period)
+        r["sde"] = float(full.sde_max)
+        for k in ks:
+            t1 = time.perf_counter()
+            res, searched, fell = gtls.tls_search_pruned(ctx, net, c["t"], c["y"], c["dy"], grid, durs, tm, C4_PMIN,
+                                                         C4_PMAX, k, -1e300, prm)
+            r[f"net{k}"] = (int(res.best_period), float(res.sde_max), time.perf_counter() - t1,
+                            float(searched.mean()), bool(searched[r["best"]]))
+            if not baselines:
+                continue
+            sub = np.nonzero(np.isin(gbin, prior[:k]))[0]
+            t1 = time.perf_counter()
+            pr = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], grid[sub], durs, tm, prm)
+            r[f"prior{k}"] = (int(sub[pr.best_period]), float(pr.sde_max), time.perf_counter() - t1,
+                              len(sub) / len(grid), bool(np.isin(r["best"], sub)))
+        t1 = time.perf_counter()
+        co = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], grid, durs, tm, coarse_prm) if baselines else None
+        t_coarse = time.perf_counter() - t1
+        for nref in (refines if baselines else ()):
+            t1 = time.perf_counter()
+            top = np.sort(np.argsort(-co.sde, kind="stable")[:nref])
+            fine = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], grid[top], durs, tm, prm)
+            chi2 = co.chi2.copy()
+            chi2[top] = fine.chi2
+            _, _, _, b2 = gtls.tls_sde(ctx, chi2, 91)
+            r[f"two{nref}"] = (int(b2), t_coarse + time.perf_counter() - t1, bool(np.isin(r["best"], top)))
+        rec.append(r)
+        if (i + 1) % 16 == 0:
+            log(f"evaluated {i + 1} of {n_test} test curves")
+    t_full = float(np.mean([r["t_full"] for r in rec]))
+    best_full = np.array([r["best"] for r in rec])
+    strong = np.array([r["sde"] >= 7.0 for r in rec])
+    rows = []
+    for name in [f"net{k}" for k in ks] + ([f"prior{k}" for k in ks] if baselines else []):
+        b = np.array([r[name][0] for r in rec])
+        s = np.array([r[name][1] for r in rec])
+        tt = np.array([r[name][2] for r in rec])
+        frac = float(np.mean([r[name][3] for r in rec]))
+        inside = float(np.mean([r[name][4] for r in rec]))
+        for thr in accepts:
+            fb = s < thr
+            fin = np.where(fb, best_full, b)
+            t = float(np.mean(tt + fb * np.array([r["t_full"] for r in rec])))
+            rows.append({"method": name, "accept_sde": thr, "grid_fraction": frac, "best_inside": inside,
+                         "fallback": float(fb.mean()), "recall": float(np.mean(fin == best_full)),
+                         "recall_sde7": float(np.mean((fin == best_full)[strong])) if strong.any() else None,
+                         "s_per_curve": t, "speedup": t_full / t})
+    for nref in (refines if baselines else ()):
+        b = np.array([r[f"two{nref}"][0] for r in rec])
+        t = float(np.mean([r[f"two{nref}"][1] for r in rec]))
+        rows.append({"method": f"two_stage_top{nref}", "accept_sde": None, "grid_fraction": nref / len(grid),
+                     "best_inside": float(np.mean([r[f"two{nref}"][2] for r in rec])), "fallback": 0.0,
+                     "recall": float(np.mean(b == best_full)),
+                     "recall_sde7": float(np.mean((b == best_full)[strong])) if strong.any() else None,
+                     "s_per_curve": t, "speedup": t_full / t})
+    out = {"workload": "proposal_3000d", "n_train": int(len(idx)), "n_test": n_test, "steps": steps, "batch": batch,
+           "lr": lr, "grid_periods": int(len(grid)), "final_loss": float(np.mean(losses[-50:])),
+           "train_seconds": t_train, "t_full_s_per_curve": t_full, "frac_test_sde7": float(strong.mean()),
+           "pretrain_views": n_pre, "pretrain_steps": pre_steps if pretrain > 0 else 0, "pretrain_seconds": t_pre,
+           "rows": rows}
+    net.close()
+    ctx.close()
+    return out
+
+
+def c4_main(argv=None):
+    ap = argparse.ArgumentParser(description="learned proposal on 3000-day curves")
+    ap.add_argument("mode", choices=["label", "eval"])
+    ap.add_argument("--start", type=int, default=0)
+    ap.add_argument("--stop", type=int, default=64)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--labels", nargs="*", default=[])
+    ap.add_argument("--test", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=600)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--pretrain", type=int, default=0, help="eval: curves for injected-period pretraining")
+    ap.add_argument("--pre-steps", type=int, default=2000)
+    ap.add_argument("--no-baselines", action="store_true", help="eval: score the network only")
+    a = ap.parse_args(argv)
+    log = lambda m: print(f"[learned-c4] {m}", file=sys.stderr, flush=True)
+    if a.mode == "label":
+        c4_label(a.start, a.stop, a.out, log)
+    else:
+        res = c4_eval(a.labels, a.test, a.steps, a.batch, a.lr, log=log, pretrain=a.pretrain,
+                      pre_steps=a.pre_steps, baselines=not a.no_baselines)
+        s = json.dumps(res)
+        print(s, flush=True)
+        with open(a.out, "w") as f:
+            f.write(s + "\n")
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] in ("label", "eval"):
+        c4_main()
+    else:
+        main()

@@ -98,3 +98,26 @@ def test_tess_full_grid_fp32c(ctx, oracle):
     res = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm,
                           gtls.gtls_params_default(dt0=0.1, precision=gtls.GTLS_FP32C))
     check_fp32c(oracle, c, periods, durs, tm, res, fx, "tess fp32c")
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_proposal_label_matches_oracle(ctx, k):
+    """The label of a learned-proposal training curve (the full-grid best
+    period and its SDE, 418,590 periods at T0 step 0.1) as the library's search
+    gives it and as the oracle gave it (tests/golden/make_fullgrid.py
+    proposal_<k>).  Two curves are re-labelled: the oracle takes about 45
+    minutes per curve on 7 cores."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("make_fullgrid", os.path.join(HERE, "golden", "make_fullgrid.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    name = f"proposal_{k}"
+    c, periods, durs, tm = mk.workload(name)
+    fx = np.load(mk.path_of(name))
+    assert str(fx["digest"]) == mk.input_digest(c, periods, durs, tm), "inputs differ from the fixture's"
+    print(f"[fullgrid] {name}: n={len(c['t'])} periods={len(periods)}", flush=True)
+    prm = gtls.gtls_params_default(dt0=float(fx["dt0"]))
+    res = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, prm)
+    assert res.best_period == int(fx["best_period"])
+    assert res.sde_max == pytest.approx(float(fx["sde_max"]), rel=RTOL64)
+    assert res.n_evals == int(fx["n_evals"])
