@@ -193,16 +193,16 @@ def cnn_bench(args):
 
 def sort_bytes(n: int, periods, durs, prm) -> float:
     """Algorithmic HBM bytes of the fold + sort + pad stage for one search:
-    per element-period 8 B of t, three radix passes over the packed 8-byte
-    (key, index) word (the first computes it: 8 B written; the others read
-    and write it: 32 B), and the padded residuals, 8 B (4 B in FP32C) per
-    position over n + D_max(P) positions, plus the 16 B (8 B) prefix sums in
-    MEAN mode (per-point weights, absent from these workloads, would add as
-    much again as the residuals)."""
+    per element-period 8 B of t, the packed 8-byte (key, index) word written
+    by the top-digit pass and read and written again by the LDS-tile pass
+    (24 B), and the padded residuals, 8 B (4 B in FP32C) per position over
+    n + D_max(P) positions, plus the 16 B (8 B) prefix sums in MEAN mode
+    (per-point weights, absent from these workloads, would add as much again
+    as the residuals)."""
     dmax = _valid_d(n, periods, durs, prm).max(axis=1)
     es = 4.0 if prm.precision == 1 else 8.0
     per_pos = es + ((8.0 if prm.precision == 1 else 16.0) if prm.depth_mode == 1 else 0.0)
-    return float(np.sum(8.0 * n + 8.0 * n + 32.0 * n + per_pos * (n + dmax)))
+    return float(np.sum(8.0 * n + 24.0 * n + per_pos * (n + dmax)))
 
 
 def _valid_d(n: int, periods, durs, prm):
