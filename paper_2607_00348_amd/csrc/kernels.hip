@@ -1,7 +1,7 @@
 // HIP kernels of the TLS search for gfx950 (MI355X) and their launchers.
 //
 // Per trial period P (Sect. 2.3 of the GTLS paper):
-//   k_fold_sort   one 1024-thread workgroup per period: phase fold on raw
+//   k_fold_sort   one 512-thread workgroup per period, two per CU: phase fold on raw
 //                 times (Sect. 2.3.1) and the order of the points by (FP64
 //                 phase, index), in two phases over 32-bit fixed-point phase
 //                 keys: one counting pass over HBM by the top 8 key bits,
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_chi2_null(const double* __restrict__ y,
 // one-period-per-workgroup kernel (NT = 1024) and the batched persistent
 // kernel (NT = 256).
 
-constexpr int kSortThreads = 1024;
+constexpr int kSortThreads = 512;
 constexpr int kSortItems = 8;
 
 // Error-free sum of two floats (Knuth's TwoSum).
@@ -596,7 +596,7 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
 // copies to be rewritten, when a bucket holds more than NT * ITEMS points or
 // a bin more than kBinCap (phases bunched within 2^-16 of a period); the
 // caller then runs fold_sort_core.
-constexpr int kTileBuckets = 32;
+constexpr int kTileBuckets = 16;
 constexpr int kBins = kTileBuckets * 256;
 constexpr uint32_t kBinCap = 64;
 
@@ -992,7 +992,7 @@ struct SortArgs {
 };
 
 // One workgroup per period of the batch.
-__global__ __launch_bounds__(kSortThreads) void k_fold_sort(SortArgs a) {
+__global__ __launch_bounds__(kSortThreads, 4) void k_fold_sort(SortArgs a) {
     __shared__ SortShared<kSortThreads> sh;
     __shared__ SortTwoPhase<kSortThreads> sx;
     const int pl = blockIdx.x;

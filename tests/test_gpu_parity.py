@@ -75,11 +75,11 @@ def test_fold_sort_with_phase_ties(ctx, oracle):
 
 
 def test_fold_sort_sizes_and_clustered_phases(ctx, oracle):
-    """Sizes around the 8192-word LDS tile, and phases bunched within 1/256 of
-    a period: a bucket of the top key digit then holds more points than one
-    LDS tile, and the sort takes its three-pass route."""
+    """Sizes around the sort's 4096- and 8192-word tiles, and phases bunched
+    within 1/256 of a period: a bucket of the top key digit then holds more
+    points than one LDS tile, and the sort takes its three-pass route."""
     g = synth.rng(17)
-    for n in (1, 2, 63, 8192, 8193, 16389):
+    for n in (1, 2, 63, 4096, 4097, 8192, 8193, 16389):
         t = np.sort(g.uniform(0.0, 300.0, n))
         for p in (0.37, 11.0, 290.0):
             _say("fold_sort size", n, p)
