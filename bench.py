@@ -108,9 +108,10 @@ def survey_bench(args):
         grids.append(gtls.gtls_period_grid_ofir(span, 3.0))
     durs = gtls.gtls_duration_grid(float(min(gr[0] for gr in grids)), 1500.0, 20)
     tm = gtls.gtls_template_quadratic(0.4, 0.25, 0.01, 0.0, 1024)
+    route = {} if args.route_min is None else {"batch_route_min": args.route_min}
     prm = gtls.gtls_params_default(dt0=args.dt0,
                                    precision=(gtls.GTLS_FP32C if args.precision == "fp32c" else gtls.GTLS_FP64),
-                                   batch_route_min=args.route_min)
+                                   **route)
     off = np.cumsum([0] + [len(c["t"]) for c in curves])
     poff = np.cumsum([0] + [len(gr) for gr in grids])
     dev = torch.device("cuda:0")
@@ -152,7 +153,7 @@ def survey_bench(args):
             "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
             "config": {"workload": "kepler_survey_sample", "curves": len(curves), "points": int(off[-1]),
                        "items": npd, "durations": len(durs), "dt0": args.dt0, "precision": args.precision,
-                       "route_min": args.route_min},
+                       "route_min": int(prm.batch_route_min)},
             "evals_per_s": n_evals / el}
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -269,9 +270,9 @@ def main():
     ap.add_argument("--workload", default="kepler_3000d",
                     choices=["kepler_3000d", "kepler_90d", "tess_13sector", "survey", "cnn_train"])
     ap.add_argument("--curves", type=int, default=32, help="survey sample size (--workload survey)")
-    ap.add_argument("--route-min", type=int, default=0,
+    ap.add_argument("--route-min", type=int, default=None,
                     help="survey: curves of at least this many points go through the single-curve kernels "
-                         "(0: all in the persistent launch)")
+                         "(default: the library's, 3000; 0: all in the persistent launch)")
     ap.add_argument("--dt0", type=float, default=0.1)
     ap.add_argument("--depth-mode", choices=["wls", "mean"], default="wls")
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")

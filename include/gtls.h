@@ -65,8 +65,9 @@ typedef struct {
     int32_t batch_route_min; /* batched calls only: curves of at least this many
                               points are searched one after the other by the
                               single-curve kernels instead of the persistent
-                              launch (identical results); 0 (default): every
-                              curve in the persistent launch                  */
+                              launch (identical results); default 3000, where
+                              the two take about the same time; 0: every curve
+                              in the persistent launch                        */
 } gtls_params;
 
 /* Per-period outputs (arrays of n_periods, caller-owned) and summaries.
@@ -207,9 +208,9 @@ gtls_status tls_search_dev_noalloc(gtls_ctx *ctx, const double *time, const doub
 
 /* Batched survey: many light curves searched in one persistent launch over
  * (curve, period) work items (Sect. 2.3-2.4 per curve); with
- * params->batch_route_min > 0, curves of at least that many points are
- * searched one after the other by the single-curve kernels instead (faster
- * for long curves; identical results).
+ * params->batch_route_min > 0 (default 3000), curves of at least that many
+ * points are searched one after the other by the single-curve kernels
+ * instead (faster for long curves; identical results).
  *   offsets [n_curves + 1], host: curve c owns points
  *     [offsets[c], offsets[c + 1]) of time/flux/dy; offsets[0] = 0, each
  *     curve has 3 <= n_c <= 2^27 points (same rules as tls_search).

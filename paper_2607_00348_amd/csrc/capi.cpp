@@ -93,7 +93,7 @@ void gtls_params_default(gtls_params* p) {
     p->depth_mode = GTLS_DEPTH_WLS;
     p->precision = GTLS_FP64;
     p->median_window = 91;
-    p->batch_route_min = 0;
+    p->batch_route_min = 3000;
 }
 
 gtls_status gtls_create(gtls_ctx** out, int device, void* hip_stream) {

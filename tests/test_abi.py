@@ -30,7 +30,7 @@ def test_params_default():
     p = gtls.gtls_params_default()
     assert (p.dt0, p.envelope, p.k_min, p.k_max, p.q_cap) == (0.0, 1, 20.05, 620.84, 0.15)
     assert (p.depth_mode, p.precision, p.median_window, p.batch_route_min) == (gtls.GTLS_DEPTH_WLS, gtls.GTLS_FP64,
-                                                                               91, 0)
+                                                                               91, 3000)
 
 
 def test_null_context_is_rejected():

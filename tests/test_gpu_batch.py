@@ -75,7 +75,7 @@ def test_batch_equals_single_curve(ctx, oracle, kw, varying):
     packed = _pack(oracle, curves)
     durs = oracle.duration_grid(0.5, 100.0, 12)
     tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 256)
-    prm = gtls.gtls_params_default(**kw)
+    prm = gtls.gtls_params_default(batch_route_min=0, **kw)
     offs, t, y, dy, poffs, periods, grids = packed
     print("batch", kw, [len(c["t"]) for c in curves], flush=True)
     res = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
@@ -92,7 +92,7 @@ def test_batch_matches_oracle(ctx, oracle):
     tm = oracle.template_quadratic(0.4, 0.25, 0.02, 0.0, 128)
     offs, t, y, dy, poffs, periods, grids = packed
     print("batch vs oracle", flush=True)
-    res = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm)
+    res = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, gtls.gtls_params_default(batch_route_min=0))
     for k, c in enumerate(curves):
         ref = oracle.tls_search(c["t"], c["y"], c["dy"], grids[k], durs, tm, threads=THREADS)
         sl = slice(poffs[k], poffs[k + 1])
@@ -129,7 +129,7 @@ def test_routed_batch_matches_oracle(ctx, oracle, dt0):
     again = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
     assert np.array_equal(again.chi2, res.chi2) and np.array_equal(again.sde, res.sde)
     whole = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm,
-                                  gtls.gtls_params_default(dt0=dt0))
+                                  gtls.gtls_params_default(dt0=dt0, batch_route_min=0))
     for k in ("chi2", "best_dur", "best_start", "depth", "sde"):
         assert np.array_equal(getattr(whole, k), getattr(res, k)), k
     for k in ("chi2_null", "sde_max", "n_evals", "n_macs", "best_period"):
@@ -156,11 +156,12 @@ def test_batch_graph_replays_on_device_buffers(ctx, oracle):
     summ = torch.zeros(len(curves) * 5, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
     dctx = gtls.Context(0, stream.cuda_stream)
+    prm = gtls.gtls_params_default(batch_route_min=0)      # every curve in the captured persistent launch
     first = None
     for rep in range(4):
         print("graph replay", rep, flush=True)
         gtls.tls_search_batch_dev(dctx, offs, t_d.data_ptr(), y_d.data_ptr(), dy_d.data_ptr(), poffs,
-                                  p_d.data_ptr(), d_d.data_ptr(), len(durs), tm_d.data_ptr(), len(tm), None,
+                                  p_d.data_ptr(), d_d.data_ptr(), len(durs), tm_d.data_ptr(), len(tm), prm,
                                   outs["chi2"].data_ptr(), bd.data_ptr(), bs.data_ptr(), outs["depth"].data_ptr(),
                                   outs["t0"].data_ptr(), outs["sr"].data_ptr(), outs["raw"].data_ptr(),
                                   outs["sde"].data_ptr(), summ.data_ptr())
@@ -168,7 +169,7 @@ def test_batch_graph_replays_on_device_buffers(ctx, oracle):
         got = (outs["chi2"].cpu().numpy().copy(), bs.cpu().numpy().copy(), outs["sde"].cpu().numpy().copy())
         if first is None:
             first = got
-            ref = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm)
+            ref = gtls.tls_search_batch(ctx, offs, t, y, dy, poffs, periods, durs, tm, prm)
             assert np.array_equal(first[0], ref.chi2) and np.array_equal(first[1], ref.best_start)
         else:
             for a, b in zip(first, got):
@@ -215,8 +216,8 @@ def test_batch_graph_key_covers_params_and_outputs(ctx, oracle):
 
     stream = torch.cuda.current_stream()
     dctx = gtls.Context(0, stream.cuda_stream)
-    p1 = gtls.gtls_params_default(dt0=0.1)
-    p2 = gtls.gtls_params_default(dt0=0.1, q_cap=0.05, k_max=300.0)
+    p1 = gtls.gtls_params_default(dt0=0.1, batch_route_min=0)
+    p2 = gtls.gtls_params_default(dt0=0.1, q_cap=0.05, k_max=300.0, batch_route_min=0)
     o1 = outputs()
     print("graph key: first call", flush=True)
     first = run(dctx, p1, o1)
