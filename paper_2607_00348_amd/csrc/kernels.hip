@@ -1681,16 +1681,16 @@ __device__ Best strided_windows_coop_r(int R, const SlideItem& si, int64_t m_lo,
 // ------------------------------------------------------------------------
 // Row-packed strided slide (single-curve search).  A wave is four rows of 16
 // lanes; each row works on windows of one strided item (period, duration),
-// so four small items (the same duration at four neighbouring periods of an
-// XCD's list) share a wave instead of leaving most of its lanes idle, while
-// an item with many windows fills all four rows itself.  Within a row the
+// so small items (the same duration at neighbouring periods of an XCD's
+// list) share a wave instead of leaving most of its lanes idle, while an
+// item with many windows fills all four rows itself.  Within a row the
 // template points are broadcast from a lane of the row (DPP row broadcast),
 // so each row follows its own item's stride and duration.  The wave's loop
 // runs over the longest run of its rows; a shorter row meets template zeros
 // past its run, which leaves its sums unchanged.
 constexpr int kRowLanes = 16;
 constexpr int kRowMax = 64;          // rows per strided item
-constexpr int kCellItems = 4;        // neighbouring periods whose rows share waves
+constexpr int kCellItems = 2;        // neighbouring periods whose rows share waves
 
 struct RowItem {
     const void* rp;                  // T padded residuals of the row's period
@@ -1748,8 +1748,11 @@ __device__ void strided_rows(const RowItem (&ri)[4], Best& best, int64_t& evals,
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t klo = c0 - (int64_t)r * s;
-            const int64_t kc = klo <= -2 * kSC ? -2 * kSC : (klo >= D ? D : klo);
-            tv[r] = load_at<TPair>(tbase, (uint32_t)(kc + 2 * kSC) * (uint32_t)sizeof(T) + tl);
+            // a block wholly before or after the window is zeros: not loaded
+            if (klo > -2 * kSC && klo < D)
+                tv[r] = load_at<TPair>(tbase, (uint32_t)(klo + 2 * kSC) * (uint32_t)sizeof(T) + tl);
+            else
+                tv[r] = TPair{(T)0, (T)0};
         }
     };
     auto stage_get = [&](const T* rowp, T (&x)[kSC]) {
