@@ -586,18 +586,19 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
 //      the tile gathered in bucket order in LDS and written to the buckets'
 //      runs of A (t -> A);
 //   2. LDS tiles of whole buckets (at most NT * ITEMS points and
-//      kTileBuckets buckets): the same counting step over the next 8 key bits
-//      of each bucket (kTileBuckets * 256 bins); each word's place in its bin
+//      kTileBuckets buckets): the same counting step over the next kSubBits
+//      key bits of each bucket (kBins bins); each word's place in its bin
 //      is the number of the bin's words that precede it in (key, phase,
 //      index) order; the tile is written back to A in place with its padded
 //      copies.
 // A then holds (32-bit key << 32 | index) in phase order; its indices are
 // those of the three-pass sort.  Returns false, leaving A and the padded
 // copies to be rewritten, when a bucket holds more than NT * ITEMS points or
-// a bin more than kBinCap (phases bunched within 2^-16 of a period); the
+// a bin more than kBinCap (phases bunched within 2^-17 of a period); the
 // caller then runs fold_sort_core.
-constexpr int kTileBuckets = 16;
-constexpr int kBins = kTileBuckets * 256;
+constexpr int kTileBuckets = 8;
+constexpr int kSubBits = 9;                          // key bits below the bucket that pick a bin
+constexpr int kBins = kTileBuckets << kSubBits;
 constexpr uint32_t kBinCap = 64;
 
 template <int NT>
@@ -766,14 +767,14 @@ __device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, doub
         load(j, item);
         const uint32_t base = tile_base(j);
         const int m = (int)(tile_end(j) - base);
-        const uint32_t bin0 = (uint32_t)sx.tiles[j] << 8;
-        const int nbins = (sx.tiles[j + 1] - sx.tiles[j]) * 256;
+        const uint32_t bin0 = (uint32_t)sx.tiles[j] << kSubBits;
+        const int nbins = (sx.tiles[j + 1] - sx.tiles[j]) << kSubBits;
         const int valid = seg_valid<ITEMS>(wave * 64 * ITEMS, m);
         for (int k = tid; k < nbins; k += NT) sx.bins[k] = 0;
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e)
-            if (e * 64 + lane < valid) rk[e] = atomicAdd(&sx.bins[(uint32_t)(item[e] >> 48) - bin0], 1u);
+            if (e * 64 + lane < valid) rk[e] = atomicAdd(&sx.bins[(uint32_t)(item[e] >> (56 - kSubBits)) - bin0], 1u);
         __syncthreads();
         // exclusive scan of the nbins counts: BPT consecutive bins per thread
         uint32_t c[BPT], sum = 0;
@@ -812,7 +813,7 @@ __device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, doub
         for (int e = 0; e < ITEMS; ++e) {
             span[e] = 0u;
             if (e * 64 + lane < valid) {
-                const uint32_t b = (uint32_t)(item[e] >> 48) - bin0;
+                const uint32_t b = (uint32_t)(item[e] >> (56 - kSubBits)) - bin0;
                 const uint32_t r0 = sx.bins[b];
                 const uint32_t r1 = (int)b + 1 < nbins ? sx.bins[b + 1] : (uint32_t)m;
                 span[e] = r0 | (r1 << 16);

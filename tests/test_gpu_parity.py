@@ -74,6 +74,30 @@ def test_fold_sort_with_phase_ties(ctx, oracle):
         assert np.array_equal(got, oracle.fold_sort(t, p))
 
 
+def test_search_is_deterministic(ctx, oracle):
+    """Two searches of one curve, the second on a fresh context, give the
+    same bits everywhere (the sort's atomic counts are unordered, but its
+    final rank is a total order; every reduction runs in a fixed order)."""
+    c = synth.curve_random(77, n=30011, inject=True)
+    span = c["t"].max() - c["t"].min()
+    periods = oracle.period_grid_ofir(span, 3.0, pmin_days=0.5, pmax_days=span / 2)
+    durs = oracle.duration_grid(0.5, 100.0, 16)
+    tm = oracle.template_quadratic(0.4, 0.25, 0.01, 0.0, 512)
+    for prm in (gtls.gtls_params_default(dt0=0.1), gtls.gtls_params_default(dt0=0.05, depth_mode=1)):
+        _say("determinism", len(periods), prm.dt0, prm.depth_mode)
+        a = gtls.tls_search(ctx, c["t"], c["y"], c["dy"], periods, durs, tm, prm)
+        other = gtls.Context(0)
+        b = gtls.tls_search(other, c["t"], c["y"], c["dy"], periods, durs, tm, prm)
+        other.close()
+        for k in ("chi2", "best_dur", "best_start", "depth", "t0", "sr", "sde"):
+            x, y = getattr(a, k), getattr(b, k)
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), k
+        assert (a.best_period, a.sde_max, a.n_evals) == (b.best_period, b.sde_max, b.n_evals)
+        perm1 = gtls.tls_fold_sort(ctx, c["t"], periods[::97])
+        perm2 = gtls.tls_fold_sort(ctx, c["t"], periods[::97])
+        assert np.array_equal(perm1, perm2)
+
+
 def test_fold_sort_sizes_and_clustered_phases(ctx, oracle):
     """Sizes around the sort's 4096- and 8192-word tiles, and phases bunched
     within 1/256 of a period: a bucket of the top key digit then holds more
