@@ -239,12 +239,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
     }
 }
 
-// dW[co][k][ci] partials: one wave per (sample, tap k) walks the sample's
-// 4096 positions in 256-position chunks (K = 256 positions = 16 MFMA steps
-// per chunk, operands staged through LDS), accumulating every chunk into the
-// same MFMA accumulators; the tap-0 wave also sums dz per channel (the bias
-// gradient's partial).  The partials are then reduced over the samples in a
-// fixed order, so gradients are deterministic.
+// dW[co][k][ci] partials per sample (and the bias gradient's, dz summed per
+// channel), reduced over the samples in a fixed order afterwards, so
+// gradients are deterministic.
 struct WGradArgs {
     const __bf16* dz;        // [B][L][32]
     const __bf16* in;        // [B][L][cin]
@@ -254,49 +251,99 @@ struct WGradArgs {
     float* bpartial;         // [B][32]
 };
 
-constexpr int kWgChunk = 256;
+constexpr int kWgWaves = 4;          // waves per sample, each over L / kWgWaves positions
+constexpr int kWgChunk = 64;         // positions per LDS chunk of a wave
+constexpr int kWgPad = C + 8;        // LDS row stride in bf16 (80 bytes: 16-byte rows, spread banks)
+static_assert(L % (kWgWaves * kWgChunk) == 0 && kWgChunk % 16 == 0 && C % 8 == 0, "wgrad tiling");
 
-__global__ __launch_bounds__(64) void k_conv_wgrad(WGradArgs a) {
-    __shared__ __bf16 dzs[kWgChunk][C + 2];
-    __shared__ __bf16 ins[kWgChunk + KW - 1][C + 2];
-    const int lane = threadIdx.x;
-    const int k = blockIdx.y;
+// One workgroup per sample b.  Wave w sums the positions [w L/4, (w+1) L/4)
+// for all KW taps at once (dW_k[co][ci] += dz[pos][co] in[pos + k - 3][ci]:
+// one 32x32x16 MFMA per tap and 16 positions, the dz operand shared by the
+// taps), from chunks staged in its own LDS rows with 16-byte loads.  The
+// waves' sums are then added in wave order through LDS, and the bias
+// gradient likewise, so the per-sample partials are deterministic.
+__global__ __launch_bounds__(64 * kWgWaves) void k_conv_wgrad(WGradArgs a) {
+    __shared__ __align__(16) __bf16 dzs[kWgWaves][kWgChunk][kWgPad];
+    __shared__ __align__(16) __bf16 ins[kWgWaves][kWgChunk + KW - 1][kWgPad];
+    __shared__ float red[C * KW * C];
+    __shared__ float bred[kWgWaves][C];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int b = blockIdx.x;
     const int row = lane & 31, half = lane >> 5;
-    floatx16 acc;
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int cin = a.cin;
+    floatx16 acc[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k)
+        for (int r = 0; r < 16; ++r) acc[k][r] = 0.0f;
     float bsum = 0.0f;
-    for (int p0 = 0; p0 < L; p0 += kWgChunk) {
-        __syncthreads();
-        for (int e = lane; e < kWgChunk * C; e += 64) {
-            const int pp = e / C, cc = e - pp * C;
-            dzs[pp][cc] = a.dz[((size_t)b * L + p0 + pp) * C + cc];
+    const __bf16* dzb = a.dz + (size_t)b * L * C;
+    const __bf16* inb = a.in + (size_t)b * L * cin;
+    const int pbeg = w * (L / kWgWaves), pend = pbeg + L / kWgWaves;
+    for (int p0 = pbeg; p0 < pend; p0 += kWgChunk) {
+        // dz rows p0 .. p0 + kWgChunk - 1, eight channels per 16-byte piece
+        for (int e = lane; e < kWgChunk * (C / 8); e += 64) {
+            const int pp = e / (C / 8), c8 = (e % (C / 8)) * 8;
+            *reinterpret_cast<uint4*>(&dzs[w][pp][c8]) =
+                *reinterpret_cast<const uint4*>(dzb + (size_t)(p0 + pp) * C + c8);
         }
-        for (int e = lane; e < (kWgChunk + KW - 1) * a.cin; e += 64) {
-            const int pp = e / a.cin, cc = e - pp * a.cin;
-            const int pos = p0 + pp - 3;
-            ins[pp][cc] = (pos >= 0 && pos < L) ? a.in[((size_t)b * L + pos) * a.cin + cc] : (__bf16)0.0f;
-        }
-        __syncthreads();
-        for (int s = 0; s < kWgChunk / 16; ++s) {
-            bf16x8 av, bv;
-            for (int q = 0; q < 8; ++q) {
-                const int pp = 16 * s + 8 * half + q;
-                av[q] = dzs[pp][row];                                           // A[co][pos]
-                bv[q] = (row < a.cin) ? ins[pp + k][row] : (__bf16)0.0f;        // B[pos][ci]
+        // input rows p0 - 3 .. p0 + kWgChunk + 2 (zeros outside the curve)
+        if (cin == C) {
+            for (int e = lane; e < (kWgChunk + KW - 1) * (C / 8); e += 64) {
+                const int pp = e / (C / 8), c8 = (e % (C / 8)) * 8;
+                const int pos = p0 + pp - 3;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (pos >= 0 && pos < L) v = *reinterpret_cast<const uint4*>(inb + (size_t)pos * C + c8);
+                *reinterpret_cast<uint4*>(&ins[w][pp][c8]) = v;
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        } else {
+            for (int e = lane; e < (kWgChunk + KW - 1) * cin; e += 64) {
+                const int pp = e / cin, cc = e - pp * cin;
+                const int pos = p0 + pp - 3;
+                ins[w][pp][cc] = (pos >= 0 && pos < L) ? inb[(size_t)pos * cin + cc] : (__bf16)0.0f;
+            }
         }
-        if (k == 0 && lane < C)
-            for (int pp = 0; pp < kWgChunk; ++pp) bsum += (float)dzs[pp][lane];
+        __syncthreads();
+        for (int st = 0; st < kWgChunk / 16; ++st) {
+            bf16x8 av;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) av[q] = dzs[w][16 * st + 8 * half + q][row];         // A[co][pos]
+#pragma unroll
+            for (int k = 0; k < KW; ++k) {
+                bf16x8 bv;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    bv[q] = (row < cin) ? ins[w][16 * st + 8 * half + q + k][row] : (__bf16)0.0f;   // B[pos][ci]
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[k], 0, 0, 0);
+            }
+        }
+        if (lane < C)
+            for (int pp = 0; pp < kWgChunk; ++pp) bsum += (float)dzs[w][pp][lane];
+        __syncthreads();
     }
-    if (k == 0 && lane < C) a.bpartial[(size_t)b * C + lane] = bsum;
-    const int col = lane & 31;
-    if (col >= a.cin) return;
-    float* out = a.partial + (size_t)b * C * KW * a.cin;
-    for (int r = 0; r < 16; ++r) {
-        const int co = 8 * (r >> 2) + 4 * half + (r & 3);
-        out[((size_t)co * KW + k) * a.cin + col] = acc[r];
+    // the waves' sums, added in wave order
+    for (int ww = 0; ww < kWgWaves; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int k = 0; k < KW; ++k)
+                for (int r = 0; r < 16; ++r) {
+                    const int co = 8 * (r >> 2) + 4 * half + (r & 3);
+                    const int i = (co * KW + k) * C + row;
+                    red[i] = ww == 0 ? acc[k][r] : red[i] + acc[k][r];
+                }
+        }
+        __syncthreads();
+    }
+    if (lane < C) bred[w][lane] = bsum;
+    __syncthreads();
+    float* out = a.partial + (size_t)b * C * KW * cin;
+    for (int i = tid; i < C * KW * cin; i += 64 * kWgWaves) {
+        const int co = i / (KW * cin), rem = i - co * KW * cin, k = rem / cin, ci = rem - k * cin;
+        out[i] = red[(co * KW + k) * C + ci];
+    }
+    if (tid < C) {
+        float s = bred[0][tid];
+        for (int ww = 1; ww < kWgWaves; ++ww) s += bred[ww][tid];
+        a.bpartial[(size_t)b * C + tid] = s;
     }
 }
 
@@ -570,7 +617,7 @@ void cnn_backward(gtls_cnn* net, int B) {
         const __bf16* in = l == 0 ? net->x : net->h[l - 1];
         float* bpart = net->partial + (size_t)B * C * KW * C;
         WGradArgs wa{dz, in, cin, B, net->partial, bpart};
-        k_conv_wgrad<<<dim3((unsigned)B, KW), 64, 0, s>>>(wa);
+        k_conv_wgrad<<<(unsigned)B, 64 * kWgWaves, 0, s>>>(wa);
         k_wgrad_reduce<<<(unsigned)((C * KW * cin + C + 255) / 256), 256, 0, s>>>(net->partial, bpart, B, cin,
                                                                                  net->grads + w_off(l),
                                                                                  net->grads + b_off(l));
