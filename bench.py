@@ -126,12 +126,24 @@ def survey_bench(args):
     summ = torch.zeros(len(curves) * 5, dtype=torch.int64, device=dev)
     ctx = gtls.Context(0, torch.cuda.current_stream().cuda_stream)
 
+    # curves per batched call: all by default; with --chunk, consecutive chunks (each a batched call of its own,
+    # a progress line after each)
+    chunk = args.chunk if args.chunk > 0 else len(curves)
+
     def step():
-        gtls.tls_search_batch_dev(ctx, off, t_d.data_ptr(), y_d.data_ptr(), dy_d.data_ptr(), poff, p_d.data_ptr(),
-                                  d_d.data_ptr(), len(durs), tm_d.data_ptr(), len(tm), prm, outs["chi2"].data_ptr(),
-                                  bd.data_ptr(), bs.data_ptr(), outs["depth"].data_ptr(), outs["t0"].data_ptr(),
-                                  outs["sr"].data_ptr(), outs["raw"].data_ptr(), outs["sde"].data_ptr(),
-                                  summ.data_ptr())
+        for c0 in range(0, len(curves), chunk):
+            c1 = min(len(curves), c0 + chunk)
+            o = off[c0:c1 + 1] - off[c0]
+            po = poff[c0:c1 + 1] - poff[c0]
+            pt = lambda x, k: x.data_ptr() + int(k) * x.element_size()
+            gtls.tls_search_batch_dev(ctx, o, pt(t_d, off[c0]), pt(y_d, off[c0]), pt(dy_d, off[c0]), po,
+                                      pt(p_d, poff[c0]), d_d.data_ptr(), len(durs), tm_d.data_ptr(), len(tm), prm,
+                                      pt(outs["chi2"], poff[c0]), pt(bd, poff[c0]), pt(bs, poff[c0]),
+                                      pt(outs["depth"], poff[c0]), pt(outs["t0"], poff[c0]), pt(outs["sr"], poff[c0]),
+                                      pt(outs["raw"], poff[c0]), pt(outs["sde"], poff[c0]), pt(summ, 5 * c0))
+            if chunk < len(curves):
+                torch.cuda.synchronize()
+                print(f"[bench] survey: {c1} of {len(curves)} curves searched", file=sys.stderr, flush=True)
 
     print(f"[bench] survey sample: {len(curves)} curves, {off[-1]} points, {npd} (curve, period) items",
           file=sys.stderr, flush=True)
@@ -153,7 +165,7 @@ def survey_bench(args):
             "dtype": "f64" if args.precision == "fp64" else "f32", "data": "synthetic",
             "config": {"workload": "kepler_survey_sample", "curves": len(curves), "points": int(off[-1]),
                        "items": npd, "durations": len(durs), "dt0": args.dt0, "precision": args.precision,
-                       "route_min": int(prm.batch_route_min)},
+                       "route_min": int(prm.batch_route_min), "curves_per_call": chunk},
             "evals_per_s": n_evals / el}
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -270,6 +282,8 @@ def main():
     ap.add_argument("--workload", default="kepler_3000d",
                     choices=["kepler_3000d", "kepler_90d", "tess_13sector", "survey", "cnn_train"])
     ap.add_argument("--curves", type=int, default=32, help="survey sample size (--workload survey)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="survey: curves per batched call (default: the whole sample in one call)")
     ap.add_argument("--route-min", type=int, default=None,
                     help="survey: curves of at least this many points go through the single-curve kernels "
                          "(default: the library's, 3000; 0: all in the persistent launch)")
