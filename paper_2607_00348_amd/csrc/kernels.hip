@@ -370,6 +370,31 @@ __device__ __forceinline__ void wave_rank(const uint64_t (&item)[ITEMS], int val
     }
 }
 
+// cnt[d] += 1 for every active lane, aggregated over runs of equal d in
+// consecutive lanes (neighbouring points of a curve often fall into the same
+// bucket, and same-address LDS atomics serialise): the first lane of a run
+// adds the run's length.  Returns each lane's count before it (its rank
+// among the lanes counted so far with its d).  The inactive lanes are a
+// suffix of the wave; every lane of the wave calls it.
+__device__ __forceinline__ uint32_t run_atomic_add(uint32_t* cnt, uint32_t d, bool active) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t dk = active ? d : 0xffffffffu;
+    const uint32_t prev = __shfl_up(dk, 1);
+    const bool head = active && (lane == 0 || prev != dk);
+    const uint64_t heads = __ballot(head);
+    const int nact = __popcll(__ballot(active));                             // all lanes vote: outside the branch
+    const uint64_t below = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);     // lanes 0..lane
+    uint32_t base = 0;
+    if (head) {
+        const uint64_t above = heads & ~below;
+        const int next = above ? __ffsll((long long)above) - 1 : nact;
+        base = atomicAdd(&cnt[d], (uint32_t)(next - lane));
+    }
+    const uint64_t upto = heads & below;
+    const int h = (active && upto) ? 63 - __clzll((long long)upto) : lane;
+    return __shfl(base, h) + (uint32_t)(lane - h);
+}
+
 // Items of a wave segment that starts at seg0 when lim items exist.
 template <int ITEMS>
 __device__ __forceinline__ int seg_valid(int64_t seg0, int64_t lim) {
@@ -636,7 +661,7 @@ __device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, doub
         }
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e)
-            if (i0 + (int64_t)e * NT + tid < n) atomicAdd(&off[phase_key32(phase_of(tv[e], period)) >> 24], 1u);
+            (void)run_atomic_add(off, phase_key32(phase_of(tv[e], period)) >> 24, i0 + (int64_t)e * NT + tid < n);
     }
     __syncthreads();
     // wave 0: exclusive offsets of 256 counts (four per lane) into dst, and
@@ -720,7 +745,7 @@ __device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, doub
         const int valid = seg_valid<ITEMS>(tile0 + (int64_t)wave * 64 * ITEMS, n);
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e)
-            if (e * 64 + lane < valid) rk[e] = atomicAdd(&sh.tcount[(uint32_t)(item[e] >> 56)], 1u);
+            rk[e] = run_atomic_add(sh.tcount, (uint32_t)(item[e] >> 56), e * 64 + lane < valid);
         if (tile0 + TILE < n) fetch(tile0 + TILE);
         __syncthreads();
         if (wave == 0) (void)scan256(sh.tcount, sh.tstart, 0xffffffffu);
