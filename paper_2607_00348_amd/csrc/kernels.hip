@@ -619,12 +619,12 @@ __device__ void fold_sort_core(const double* __restrict__ t, int64_t n, double p
 // A then holds (32-bit key << 32 | index) in phase order; its indices are
 // those of the three-pass sort.  Returns false, leaving A and the padded
 // copies to be rewritten, when a bucket holds more than NT * ITEMS points or
-// a bin more than kBinCap (phases bunched within 2^-17 of a period); the
-// caller then runs fold_sort_core.
+// a bin more than kBinCap (more than kBinCap phases within 2^-17 of a
+// period); the caller then runs fold_sort_core.
 constexpr int kTileBuckets = 8;
 constexpr int kSubBits = 9;                          // key bits below the bucket that pick a bin
 constexpr int kBins = kTileBuckets << kSubBits;
-constexpr uint32_t kBinCap = 64;
+constexpr uint32_t kBinCap = 1024;
 
 template <int NT>
 struct SortTwoPhase {
@@ -783,11 +783,6 @@ __device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, doub
 #pragma unroll
         for (int e = 0; e < ITEMS; ++e) it[e] = wseg + e * 64 < m ? src[e * 64] : 0ull;
     };
-    // (key, FP64 phase, index) order of two words
-    auto word_less = [&](uint64_t a, uint64_t b) -> bool {
-        const uint32_t ka = (uint32_t)(a >> 32), kb = (uint32_t)(b >> 32);
-        return ka != kb ? ka < kb : key_less(a, b, t, period);
-    };
     for (int j = 0; j < ntiles; ++j) {
         load(j, item);
         const uint32_t base = tile_base(j);
@@ -868,9 +863,21 @@ __device__ bool fold_sort_twophase(const double* __restrict__ t, int64_t n, doub
 #pragma unroll
             for (int e = 0; e < ITEMS; ++e) {
                 if (ties & (1u << e)) {
+                    // (key, FP64 phase, index) order; this word's phase computed once
+                    const uint64_t me = item[e];
+                    const uint32_t kme = (uint32_t)(me >> 32);
+                    const double pme = phase_of(t[(uint32_t)me], period);
                     uint32_t r = 0u;
-                    for (uint32_t x = span[e] & 0xffffu; x < (span[e] >> 16); ++x)
-                        if (word_less(sh.buf[x], item[e])) ++r;
+                    for (uint32_t x = span[e] & 0xffffu; x < (span[e] >> 16); ++x) {
+                        const uint64_t o = sh.buf[x];
+                        const uint32_t ko = (uint32_t)(o >> 32);
+                        if (ko < kme) {
+                            ++r;
+                        } else if (ko == kme && o != me) {
+                            const double po = phase_of(t[(uint32_t)o], period);
+                            if (po < pme || (po == pme && (uint32_t)o < (uint32_t)me)) ++r;
+                        }
+                    }
                     rk[e] = r;
                 }
             }

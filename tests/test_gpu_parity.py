@@ -117,6 +117,18 @@ def test_fold_sort_sizes_and_clustered_phases(ctx, oracle):
         assert np.array_equal(got, oracle.fold_sort(t, p)), p
 
 
+def test_fold_sort_near_resonant_periods(ctx, oracle):
+    """Periods of the TESS-like grid near a ratio of small integers to the
+    2-minute cadence: up to 267 points share a 2^-17-wide phase bin, which the
+    two-phase sort ranks by comparison within the bin."""
+    c = synth.curve_tess()
+    periods = np.array([0.6215277762269412, 0.6416666118696994, 1.3708333404340887, 0.9995370623111847])
+    _say("fold_sort near-resonant", len(c["t"]))
+    got = gtls.tls_fold_sort(ctx, c["t"], periods)
+    for k, p in enumerate(periods):
+        assert np.array_equal(got[k], oracle.fold_sort(c["t"], p)), p
+
+
 def test_sde_kernel_matches_oracle(ctx, oracle):
     for n, w in ((1, 1), (50, 91), (3000, 91), (100000, 91), (4000, 5)):
         chi2 = synth.random_chi2_series(n, n)
