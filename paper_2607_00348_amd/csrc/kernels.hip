@@ -6,7 +6,7 @@
 //                 phase, index), in two phases over 32-bit fixed-point phase
 //                 keys: one counting pass over HBM by the top 8 key bits,
 //                 then LDS tiles of whole top-digit buckets ordered by the
-//                 next 8 bits and, within those bins, by rank; periods whose
+//                 next 9 bits and, within those bins, by rank; periods whose
 //                 phases bunch too tightly for the LDS tiles take a 3-pass
 //                 stable LSD radix sort over 24-bit keys (wave-ballot
 //                 ranking, equal keys fixed by FP64 phase then index).  Then
@@ -20,11 +20,15 @@
 //                 of 4096 windows of one (period, duration) item; each lane
 //                 owns 16 consecutive windows whose correlation sums run in
 //                 registers over a padded, bank-conflict-free LDS tile.
-//   k_slide_strided  T0 step s >= 2 (Sect. 2.5): persistent waves pop wave
-//                 tasks; each lane owns R windows s points apart and streams
-//                 its run of the padded curve once for all of them.
+//   k_slide_rows  T0 step s >= 2 (Sect. 2.5): persistent waves pop wave
+//                 tasks of four 16-lane rows, each row on one (period,
+//                 duration) item; each lane owns R windows s points apart and
+//                 streams its run of the padded curve once for all of them.
 //   k_reduce      per period: first best over durations -> chi2(P), depth, T0.
 //   k_sde_*       SR, SDE_raw, running-median detrend, argmax (Sect. 2.4).
+//   k_batch       many curves: one persistent kernel over (curve, period)
+//                 items, each folded, sorted, padded and slid by one
+//                 workgroup.
 //
 // Every floating-point expression that decides a result is written to give
 // the same IEEE operations in the same order as a plain sequential
