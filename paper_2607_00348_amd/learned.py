@@ -7,12 +7,20 @@ of the full-grid search, computed with the batched GPU search (which is
 bit-exact against the CPU oracle).  Everything here calls the C ABI through
 ``gtls``; the oracle is not used.
 
-Run: ``python -m paper_2607_00348_amd.learned --train 8192 --test 1024``
-writes a JSON summary: recall@k of the network and of the prior-only ranking
-(is the full-grid best period's bin among the top k), the final recall of the
-best period (curves whose pruned search peaks below SDE ``--accept`` fall back
-to the full grid, which also judges recall), and the curves/hour and speed-up
-of view + network + pruned search + fallback over the plain full-grid search.
+Two workloads:
+
+* 90-day stand-in curves (``training_curve``, periods 0.5-45 d):
+  ``python -m paper_2607_00348_amd.learned --train 8192 --test 1024`` writes a
+  JSON summary: recall@k of the network and of the prior-only ranking (is the
+  full-grid best period's bin among the top k), the final recall of the best
+  period (curves whose pruned search peaks below SDE ``--accept`` fall back to
+  the full grid, which also judges recall), and the curves/hour and speed-up of
+  view + network + pruned search + fallback over the plain full-grid search.
+* 3000-day curves (``synth.proposal_curve``, periods 0.5-1500 d, 418,590-period
+  grid): ``label`` writes the full-grid labels of a range of curves, ``eval``
+  trains on them (optionally after pretraining on the injected-period bins of
+  further curves) and scores held-out curves against the full grid, the
+  prior-only ranking and the coarse two-stage pass.
 """
 from __future__ import annotations
 
@@ -241,7 +249,7 @@ def main(argv=None):
 # (Sect. 2.5: T0 step 0.5 over the grid, then the T0 step 0.1 on the periods
 # with the largest coarse SDE).
 
-C4_PMIN, C4_PMAX, C4_DT0 = 0.5, 1500.0, 0.1
+C4_PMIN, C4_PMAX, C4_DT0 = 0.5, 1500.0, 0.1     # 3000-day curves: period range and T0 step
 
 
 def c4_inputs():
