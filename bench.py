@@ -299,8 +299,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the search shards periods across GPUs by design, "
-              "but this build measures the single-GPU kernel path; use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only (the single-GPU kernel path; sharding periods across GPUs is a "
+              "design, not measured here); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "survey":
