@@ -6,14 +6,14 @@ fixture stores, for every period of the workload's Ofir grid, the oracle's
 chi2, best duration index, best window start, depth and T0 at the T0 step
 dt0 = 0.1 (Sect. 2.5), plus the grid itself and a description of the inputs.
 The GPU tests compare every period of the library's search with these arrays.
-For two curves of the learned-proposal set (3000-day curves, the same
+For five curves of the learned-proposal set (3000-day curves, the same
 418,590-period grid) it stores only the label, the full-grid best period and
 its SDE, with the evaluation count and a digest of the oracle's chi2 array.
 
-    python tests/golden/make_fullgrid.py [kepler_3000d|tess|proposal_0|proposal_1] [--threads N]
+    python tests/golden/make_fullgrid.py [kepler_3000d|tess|proposal_<k>] [--threads N]
 
 Run time: about 15 minutes for the 3000-day curve on 8 cores, about 2 for the
-TESS-like curve, about 45 for each proposal curve on 7.
+TESS-like curve, 30 to 45 for each proposal curve on 7 or 8.
 """
 from __future__ import annotations
 
@@ -36,7 +36,7 @@ from paper_2607_00348_amd import synth  # noqa: E402
 DT0 = 0.1
 
 
-PROPOSAL_CURVES = (0, 1)
+PROPOSAL_CURVES = (0, 1, 2, 3, 4)
 
 
 def proposal_grid():
